@@ -1,0 +1,192 @@
+"""Synthetic, seeded inputs for the coupled central-moment LB step.
+
+This module holds only input construction: parameter sets and initial fields
+built from the analytic set-ups of the paper's benchmarks (arXiv 2504.09024,
+Sec. 4).  It contains none of the step's arithmetic, so both the GPU library's
+tests and the CPU oracle's tests may draw their inputs from it.
+
+Initial fields:
+  * phase field: the tanh equilibrium profile, phi = phi_m + phi_o tanh(2 zeta/W)
+    with zeta = R - |x - x_o| (Eq. CACEeq; Sec. 4.1 defines zeta);
+  * surfactant: c = c_hat(theta) / cosh^2(2 zeta/W) (Eq. ISSeq; the static drop
+    of Sec. 4.1 uses c_hat = (1 - cos theta)/2);
+  * shear flow: u = U_o (2 y/H - 1) with y measured from the lower wall plane
+    (Sec. 4.3).
+
+Every function returns ``(params, fields)``: ``params`` is a dict keyed by the
+library's parameter names, ``fields`` a dict of float64 arrays [ny][nx].
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+CS2 = 1.0 / 3.0
+
+BASE_PARAMS = dict(
+    nx=64, ny=64, bc_y="periodic", flow="none",
+    W=4.0, phi_a=1.0, phi_b=0.0, M_phi=0.1, D_s=0.01,
+    rho_a=1.0, rho_b=1.0, nu_a=0.1, nu_b=0.1, omega_zeta=1.0,
+    sigma0=0.0, beta=0.0, c_max=1.0,
+    u_wall=0.0, F_ext_x=0.0, F_ext_y=0.0, vel_period_T=0.0,
+)
+
+
+def params(**kw) -> dict:
+    p = dict(BASE_PARAMS)
+    p.update(kw)
+    return p
+
+
+def drop_fields(nx, ny, xc, yc, R, W, c_hat=None, phi_a=1.0, phi_b=0.0, y_offset=0.0):
+    """tanh drop (Eq. CACEeq) and sech^2 surfactant band (Eq. ISSeq).
+
+    Node (i, j) sits at (i, j + y_offset).  ``c_hat`` is a callable of the
+    polar angle theta (measured from +x), or a constant, or None (no
+    surfactant)."""
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None] + y_offset
+    dx = x - xc
+    dy = y - yc
+    r = np.sqrt(dx * dx + dy * dy)
+    zeta = R - r
+    phim = 0.5 * (phi_a + phi_b)
+    phio = 0.5 * (phi_a - phi_b)
+    phi = phim + phio * np.tanh(2.0 * zeta / W)
+    theta = np.arctan2(dy, dx)
+    if c_hat is None:
+        ch = np.zeros_like(phi)
+    elif callable(c_hat):
+        ch = c_hat(theta)
+    else:
+        ch = np.full_like(phi, float(c_hat))
+    c = ch / np.cosh(2.0 * zeta / W) ** 2
+    return np.ascontiguousarray(phi), np.ascontiguousarray(c)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def static_drop(n=128, R=32.0, W=4.0, D_s=0.01, M_phi=0.1, mode=1):
+    """Static drop with a cos(mode*theta) surfactant gradient, u = 0
+    (Sec. 4.1 set-up, scaled: 128x128 periodic, R = 32, W = 4, D_s = 0.01).
+    c_hat = (1 - cos(mode theta))/2."""
+    p = params(nx=n, ny=n, bc_y="periodic", flow="none", W=W, D_s=D_s, M_phi=M_phi)
+    phi, c = drop_fields(n, n, n / 2, n / 2, R, W, lambda th: 0.5 * (1.0 - np.cos(mode * th)))
+    return p, dict(phi=phi, c=c)
+
+
+def vortex_drop(n=512, R=64.0, W=4.0, U0=0.02, T=20000.0, D_s=0.01, M_phi=0.1,
+                center=None, c_hat=0.5):
+    """Drop in a prescribed time-reversing single vortex on a periodic box.
+
+    u =  U0 sin^2(pi x/L) sin(2 pi y/L) cos(pi t/T)
+    v = -U0 sin^2(pi y/L) sin(2 pi x/L) cos(pi t/T)
+    The shapes are passed as ux/uy; the library applies cos(pi t/T)."""
+    if center is None:
+        center = (n / 2, 0.75 * n)
+    p = params(nx=n, ny=n, bc_y="periodic", flow="prescribed", W=W, D_s=D_s, M_phi=M_phi,
+               vel_period_T=T)
+    phi, c = drop_fields(n, n, center[0], center[1], R, W, c_hat)
+    L = float(n)
+    x = np.arange(n, dtype=np.float64)[None, :]
+    y = np.arange(n, dtype=np.float64)[:, None]
+    ux = U0 * np.sin(np.pi * x / L) ** 2 * np.sin(2 * np.pi * y / L)
+    uy = -U0 * np.sin(np.pi * y / L) ** 2 * np.sin(2 * np.pi * x / L)
+    ux = np.ascontiguousarray(np.broadcast_to(ux, (n, n)))
+    uy = np.ascontiguousarray(np.broadcast_to(uy, (n, n)))
+    return p, dict(phi=phi, c=c, ux=ux, uy=uy)
+
+
+def shear_drop(nx=1024, ny=512, R=None, W=4.0, Ca=0.3, E=0.2, c0=0.3, Re=0.1, nu=0.1,
+               Pe_s=1.0, Pe_star=0.5, rho=1.0, omega_zeta=1.0, c_max=1.0):
+    """Surfactant-laden drop in simple shear between walls moving at +-U0
+    (Sec. 4.3 set-up).  H = ny, R = H/8 unless given; drop at the channel
+    centre; Re = gdot R^2/nu; Ca = mu gdot R/sigma0; Pe* = U0 W/M_phi (the
+    paper uses 0.5); Pe_s = gdot R^2/D_s.  The velocity starts at the
+    wall-driven linear profile u = U0 (2y/H - 1), y = j + 1/2."""
+    H = float(ny)
+    if R is None:
+        R = H / 8.0
+    gdot = Re * nu / (R * R)
+    U0 = gdot * H / 2.0
+    sigma0 = rho * nu * gdot * R / Ca
+    M_phi = U0 * W / Pe_star
+    D_s = gdot * R * R / Pe_s
+    p = params(nx=nx, ny=ny, bc_y="walls", flow="coupled", W=W, M_phi=M_phi, D_s=D_s,
+               rho_a=rho, rho_b=rho, nu_a=nu, nu_b=nu, omega_zeta=omega_zeta,
+               sigma0=sigma0, beta=E, c_max=c_max, u_wall=U0)
+    phi, c = drop_fields(nx, ny, nx / 2.0, H / 2.0, R, W, c0, y_offset=0.5)
+    y = np.arange(ny, dtype=np.float64)[:, None] + 0.5
+    ux = np.ascontiguousarray(np.broadcast_to(U0 * (2.0 * y / H - 1.0), (ny, nx)))
+    uy = np.zeros((ny, nx))
+    return p, dict(phi=phi, c=c, ux=ux, uy=uy)
+
+
+def batched_shear_drops(n_sims=64, seed=2504, max_nodes=None):
+    """64 independent coupled shear-drop runs with seeded sizes and parameters
+    (numpy default_rng(seed)): ny uniform on {256, 320, ..., 512}; nx uniform
+    on multiples of 64 in [ny, 1024]; R = ny/8; Ca ~ U[0.05, 0.6];
+    E ~ U[0.1, 0.5]; c0 ~ U[0.1, 0.5]; Pe_s log-uniform on [0.5, 10];
+    Re = 0.1, nu = 0.1, Pe* = 0.5.  ``max_nodes`` scales every grid down
+    (keeping multiples of 16) for small test runs."""
+    rng = np.random.default_rng(seed)
+    sims = []
+    for _ in range(n_sims):
+        ny = int(rng.choice(np.arange(256, 513, 64)))
+        nx_choices = np.arange(((ny + 63) // 64) * 64, 1025, 64)
+        nx = int(rng.choice(nx_choices))
+        Ca = float(rng.uniform(0.05, 0.6))
+        E = float(rng.uniform(0.1, 0.5))
+        c0 = float(rng.uniform(0.1, 0.5))
+        Pe_s = float(math.exp(rng.uniform(math.log(0.5), math.log(10.0))))
+        sims.append(dict(nx=nx, ny=ny, Ca=Ca, E=E, c0=c0, Pe_s=Pe_s))
+    out = []
+    for s in sims:
+        nx, ny = s["nx"], s["ny"]
+        if max_nodes is not None and nx * ny > max_nodes:
+            f = math.sqrt(max_nodes / (nx * ny))
+            nx = max(16, int(nx * f) // 16 * 16)
+            ny = max(16, int(ny * f) // 16 * 16)
+        out.append(shear_drop(nx=nx, ny=ny, Ca=s["Ca"], E=s["E"], c0=s["c0"], Pe_s=s["Pe_s"]))
+    return out
+
+
+def flat_interface(nx=64, ny=8, W=4.0, c_hat=0.0, M_phi=0.1, D_s=0.05):
+    """Two flat tanh interfaces (normal along x) on a periodic box, with a
+    uniform c_hat sech^2 band on each: the steady profiles of Eqs. CACEeq and
+    ISSeq."""
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    x1, x2 = nx / 4.0, 3.0 * nx / 4.0
+    zeta = np.minimum(x - x1, x2 - x)
+    phi = 0.5 + 0.5 * np.tanh(2.0 * zeta / W)
+    c = c_hat / np.cosh(2.0 * zeta / W) ** 2
+    p = params(nx=nx, ny=ny, bc_y="periodic", flow="none", W=W, M_phi=M_phi, D_s=D_s)
+    return p, dict(phi=np.ascontiguousarray(np.broadcast_to(phi, (ny, nx))),
+                   c=np.ascontiguousarray(np.broadcast_to(c, (ny, nx))))
+
+
+def random_fields(nx, ny, seed=0, flow="coupled", bc_y="walls", amp=0.05, **kw):
+    """Smooth random fields (for parity tests): a drop plus low-amplitude
+    seeded noise on phi, c and u."""
+    rng = np.random.default_rng(seed)
+    p = params(nx=nx, ny=ny, bc_y=bc_y, flow=flow, **kw)
+    R = min(nx, ny) / 4.0
+    y_off = 0.5 if bc_y == "walls" else 0.0
+    phi, c = drop_fields(nx, ny, nx / 2.0 + 0.3, ny / 2.0 - 0.2, R, p["W"],
+                         lambda th: 0.2 + 0.1 * np.cos(th) + 0.05 * np.sin(3 * th),
+                         y_offset=y_off)
+    phi = phi + amp * 0.1 * rng.standard_normal(phi.shape)
+    c = np.abs(c + amp * 0.02 * rng.standard_normal(c.shape))
+    ux = amp * 0.01 * rng.standard_normal(phi.shape)
+    uy = amp * 0.01 * rng.standard_normal(phi.shape)
+    P = CS2 + amp * 1e-3 * rng.standard_normal(phi.shape)
+    return p, dict(phi=np.ascontiguousarray(phi), c=np.ascontiguousarray(c),
+                   ux=np.ascontiguousarray(ux), uy=np.ascontiguousarray(uy),
+                   P=np.ascontiguousarray(P))
+
+
+def nodes(p) -> int:
+    return int(p["nx"]) * int(p["ny"])
