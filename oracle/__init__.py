@@ -65,6 +65,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(OParams)
+        L.o_num_threads.restype = ctypes.c_int
         L.o_central_moments.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
         L.o_populations_from_central.argtypes = [dp, ctypes.c_double, ctypes.c_double, dp]
         L.o_weights.argtypes = [dp]
@@ -98,6 +99,10 @@ def _vec(x):
 
 
 # ---- single-node functions -------------------------------------------------
+
+def num_threads() -> int:
+    return int(lib().o_num_threads())
+
 
 def central_moments(q, ux, uy):
     q = _vec(q)

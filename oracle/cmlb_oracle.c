@@ -43,7 +43,9 @@
  *     d_i Phi = (1/cs^2) sum_a w_a e_ai Phi(x + e_a); the curvature is the
  *     same stencil applied to the unit normal; n = grad phi/(|grad phi|+eps),
  *     eps = 1e-12;
- *   - ghost values beyond a wall mirror the fluid rows about the wall plane;
+ *   - ghost values of phi, c and psi^ beyond a wall mirror the fluid rows
+ *     about the wall plane; the unit normal at a ghost node is computed from
+ *     the ghost values of phi like at any node;
  *   - the surface-tension force of Eq. Fs is multiplied by
  *     k_s = 3W/(8 phi_o^2) so that its integral across a tanh interface is
  *     sigma (an option selects |grad phi| in place of |grad phi|^2 with
@@ -69,6 +71,19 @@
 #include <string.h>
 
 #include "cmlb_oracle.h"
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads an OpenMP region of the oracle uses (1 without OpenMP). */
+int o_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* D2Q9 directions, Eqs. ex/ey (x component of direction 8 read as +1). */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -321,14 +336,22 @@ typedef struct {
     double *phi, *c, *phat, *psih, *nrmx, *nrmy;
 } fields_t;
 
+/* The unit-normal arrays carry one extra row below and above the grid
+ * (rows -1 and ny): at a wall the curvature stencil needs the normal at the
+ * ghost row, which is computed from the ghost values of phi like at any
+ * other node (so its wall-normal component is mirrored too). */
+#define NRM(F, p, x, y) ((F)->nrmx[(size_t)((y) + 1) * (size_t)(p)->nx + (size_t)(x)])
+#define NRMY(F, p, x, y) ((F)->nrmy[(size_t)((y) + 1) * (size_t)(p)->nx + (size_t)(x)])
+
 static void fields_alloc(const o_params* p, fields_t* F) {
     size_t n = (size_t)p->nx * p->ny;
+    size_t ne = (size_t)p->nx * (p->ny + 2);
     F->phi = calloc(n, sizeof(double));
     F->c = calloc(n, sizeof(double));
     F->phat = calloc(n, sizeof(double));
     F->psih = calloc(n, sizeof(double));
-    F->nrmx = calloc(n, sizeof(double));
-    F->nrmy = calloc(n, sizeof(double));
+    F->nrmx = calloc(ne, sizeof(double));
+    F->nrmy = calloc(ne, sizeof(double));
 }
 static void fields_free(fields_t* F) {
     free(F->phi);
@@ -364,14 +387,26 @@ static void compute_fields(const o_params* p, const double w[9], const double* f
             F->psih[IDX(p, x, y)] = sg - rho * CS2;
         }
 #pragma omp parallel for schedule(static)
-    for (int y = 0; y < ny; ++y)
+    for (int y = -1; y <= ny; ++y)
         for (int x = 0; x < nx; ++x) {
             double gx, gy;
             grad_field(p, F->phi, w, x, y, &gx, &gy);
             double mag = sqrt(gx * gx + gy * gy);
-            F->nrmx[IDX(p, x, y)] = gx / (mag + NORMAL_EPS);
-            F->nrmy[IDX(p, x, y)] = gy / (mag + NORMAL_EPS);
+            NRM(F, p, x, y) = gx / (mag + NORMAL_EPS);
+            NRMY(F, p, x, y) = gy / (mag + NORMAL_EPS);
         }
+}
+
+/* Divergence of the unit normal with the isotropic stencil.  Rows -1 and ny
+ * are the ghost rows; in y-periodic grids they equal rows ny-1 and 0. */
+static double curvature(const o_params* p, const fields_t* F, const double w[9], int x, int y) {
+    double s = 0.0;
+    for (int a = 0; a < 9; ++a) {
+        int xs = wrap_x(p, x + EX[a]);
+        int ys = y + EY[a];
+        s += w[a] * (EX[a] * NRM(F, p, xs, ys) + EY[a] * NRMY(F, p, xs, ys));
+    }
+    return s / CS2;
 }
 
 /* Steps 2-4 at one node. */
@@ -388,8 +423,8 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
 
     grad_field(p, F->phi, w, x, y, &s->gphix, &s->gphiy);
     s->gmag = sqrt(s->gphix * s->gphix + s->gphiy * s->gphiy);
-    s->nx = F->nrmx[i];
-    s->ny = F->nrmy[i];
+    s->nx = NRM(F, p, x, y);
+    s->ny = NRMY(F, p, x, y);
     const double dphi = p->phi_a - p->phi_b;
     const double phim = 0.5 * (p->phi_a + p->phi_b);
     s->theta = (4.0 / p->W) * (p->phi_a - s->phi) * (s->phi - p->phi_b) / dphi;
@@ -397,10 +432,7 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
 
     if (p->flow == O_FLOW_COUPLED) {
         /* curvature: divergence of the unit normal, same stencil */
-        double dnx_dx, dnx_dy, dny_dx, dny_dy;
-        grad_field(p, F->nrmx, w, x, y, &dnx_dx, &dnx_dy);
-        grad_field(p, F->nrmy, w, x, y, &dny_dx, &dny_dy);
-        s->curv = dnx_dx + dny_dy;
+        s->curv = curvature(p, F, w, x, y);
         grad_field(p, F->c, w, x, y, &s->gcx, &s->gcy);
         grad_field(p, F->psih, w, x, y, &s->gpsix, &s->gpsiy);
 
@@ -486,8 +518,8 @@ int o_init(const o_params* p, const double* phi, const double* c, const double* 
             double gx, gy;
             grad_field(p, F.phi, w, x, y, &gx, &gy);
             double mag = sqrt(gx * gx + gy * gy);
-            F.nrmx[IDX(p, x, y)] = gx / (mag + NORMAL_EPS);
-            F.nrmy[IDX(p, x, y)] = gy / (mag + NORMAL_EPS);
+            NRM(&F, p, x, y) = gx / (mag + NORMAL_EPS);
+            NRMY(&F, p, x, y) = gy / (mag + NORMAL_EPS);
         }
     const double dphi = p->phi_a - p->phi_b, phim = 0.5 * (p->phi_a + p->phi_b);
     int bad = 0;
@@ -497,7 +529,7 @@ int o_init(const o_params* p, const double* phi, const double* c, const double* 
             size_t i = IDX(p, x, y);
             double u = ux ? ux[i] : 0.0, v = uy ? uy[i] : 0.0;
             double ph = phi[i], cc = c[i];
-            double nxv = F.nrmx[i], nyv = F.nrmy[i];
+            double nxv = NRM(&F, p, x, y), nyv = NRMY(&F, p, x, y);
             double theta = (4.0 / p->W) * (p->phi_a - ph) * (ph - p->phi_b) / dphi;
             double theta_c = (8.0 * cc / p->W) * (phim - ph) / dphi;
             double kf[9], kh[9], qf[9], qh[9];

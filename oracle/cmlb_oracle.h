@@ -30,6 +30,7 @@ typedef struct {
     double vel_period_T;
 } o_params;
 
+int o_num_threads(void);
 void o_central_moments(const double q[9], double ux, double uy, double out[9]);
 int o_populations_from_central(const double kappa[9], double ux, double uy, double q[9]);
 void o_weights(double w[9]);

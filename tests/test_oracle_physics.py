@@ -168,3 +168,26 @@ def test_laplace_law(oracle_mod):
         vals.append(P[n // 2 - 2:n // 2 + 2, n // 2 - 2:n // 2 + 2].mean() - P[:3, :3].mean())
     ratio = np.mean(vals) / (sig / R)
     assert 0.85 < ratio < 1.02, ratio
+
+
+def test_wall_ghost_normal_mirrors(oracle_mod):
+    """Ghost rows mirror phi about the wall plane, and the normal there is
+    computed from those ghost values.  A drop centred on the lower wall plane
+    is then, seen through the ghosts, the full circle: curvature and forces in
+    the first fluid rows equal those of the full circle in a periodic box at
+    the mirrored position.  (Mirroring the normal's components as scalars
+    would flip the sign of the wall-normal part and break this.)"""
+    nx, R = 64, 12.0
+    pw = W.params(nx=nx, ny=32, bc_y="walls", flow="coupled", sigma0=1e-3)
+    phi_w, c_w = W.drop_fields(nx, 32, 32.0, -0.5, R, 4.0, 0.2)
+    sw = oracle_mod.OracleSim(oracle_mod.make_params(**pw), phi_w, c_w)
+    pp = W.params(nx=nx, ny=64, bc_y="periodic", flow="coupled", sigma0=1e-3)
+    phi_p, c_p = W.drop_fields(nx, 64, 32.0, 31.5, R, 4.0, 0.2)
+    sp = oracle_mod.OracleSim(oracle_mod.make_params(**pp), phi_p, c_p)
+    for x in (40, 43, 44, 45, 48):
+        for row in (0, 1):
+            dw = sw.diag(x, row)
+            dp = sp.diag(x, 32 + row)
+            for k in ("curv", "fsx", "fsy", "nx", "ny"):
+                assert abs(dw[k] - dp[k]) <= 1e-13 * max(1.0, abs(dp[k])), (x, row, k)
+            assert abs(dp["curv"]) > 1e-3
