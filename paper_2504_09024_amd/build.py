@@ -1,0 +1,54 @@
+"""Build ``libcmlb.so`` (the HIP library behind include/cmlb.h) for gfx950.
+
+Run ``python -m paper_2504_09024_amd.build`` or call :func:`build`.  The
+library is built in-tree next to this file so it travels with the source
+tree.  Packed FP32 instructions are disabled (``-packed-fp32-ops``): hipcc
+otherwise forms v_pk_* FP32 ops from ordinary float code.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libcmlb.so")
+SOURCES = [os.path.join(HERE, "csrc", "cmlb.hip")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "lattice.hpp")] + [
+    os.path.join(ROOT, "include", "cmlb.h")]
+ARCH = os.environ.get("CMLB_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm toolchain required to build libcmlb.so)")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wno-unused-command-line-argument",
+           *SOURCES, "-o", LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building libcmlb.so")
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def is_stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(d) > t for d in DEPS if os.path.exists(d))
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,240 @@
+"""Thin ctypes binding of the C ABI in ``include/cmlb.h``.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libcmlb.so``.  The functions keep the C names (``cmlb_create``,
+``cmlb_step``, ...); :class:`Context` wraps them for numpy users.  If the
+library has not been built, :func:`load` raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcmlb.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ERANGE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTABLE",
+                -5: "ERANGE", -6: "ESTATE"}
+FP64, FP32, FP16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16": FP16}
+BC = {"periodic": 0, "walls": 1, "moving_walls": 1}
+FLOW = {"none": 0, "prescribed": 1, "coupled": 2}
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc_y", ctypes.c_int32), ("flow", ctypes.c_int32),
+        ("W", ctypes.c_double), ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double),
+        ("M_phi", ctypes.c_double), ("D_s", ctypes.c_double),
+        ("rho_a", ctypes.c_double), ("rho_b", ctypes.c_double), ("nu_a", ctypes.c_double),
+        ("nu_b", ctypes.c_double), ("omega_zeta", ctypes.c_double),
+        ("sigma0", ctypes.c_double), ("beta", ctypes.c_double), ("c_max", ctypes.c_double),
+        ("u_wall", ctypes.c_double), ("F_ext_x", ctypes.c_double), ("F_ext_y", ctypes.c_double),
+        ("vel_period_T", ctypes.c_double),
+    ]
+
+
+EXPORTS = (
+    "cmlb_create", "cmlb_init_fields", "cmlb_step", "cmlb_read_fields", "cmlb_inventory",
+    "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
+    "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_launch_options", "cmlb_set_use_graph",
+    "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
+)
+
+_lib = None
+
+
+class CmlbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Load libcmlb.so and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2504_09024_amd.build` "
+            "(no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.cmlb_create.argtypes = [ctypes.POINTER(SimParams), ctypes.c_int32, ctypes.c_int32, vp,
+                              ctypes.POINTER(vp)]
+    L.cmlb_init_fields.argtypes = [vp, ctypes.c_int32, dp, dp, dp, dp, dp]
+    L.cmlb_step.argtypes = [vp, ctypes.c_int32]
+    L.cmlb_read_fields.argtypes = [vp, ctypes.c_int32, dp, dp, dp, dp, dp]
+    L.cmlb_inventory.argtypes = [vp, ctypes.c_int32, dp, dp]
+    L.cmlb_get_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
+    L.cmlb_set_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
+    L.cmlb_set_step_count.argtypes = [vp, ctypes.c_int64]
+    L.cmlb_fault_flags.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.cmlb_synchronize.argtypes = [vp]
+    L.cmlb_set_tile_rows.argtypes = [vp, ctypes.c_int32]
+    L.cmlb_launch_options.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.cmlb_set_use_graph.argtypes = [vp, ctypes.c_int32]
+    L.cmlb_step_count.argtypes = [vp]
+    L.cmlb_step_count.restype = ctypes.c_int64
+    L.cmlb_num_sims.argtypes = [vp]
+    L.cmlb_num_sims.restype = ctypes.c_int32
+    L.cmlb_last_error.argtypes = [vp]
+    L.cmlb_last_error.restype = ctypes.c_char_p
+    L.cmlb_destroy.argtypes = [vp]
+    L.cmlb_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape):
+    if a is None:
+        return None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if arr.shape != shape:
+        arr = arr.reshape(shape)
+    return arr
+
+
+def make_params(d: dict) -> SimParams:
+    p = SimParams()
+    for name, _ in SimParams._fields_:
+        if name not in d:
+            continue
+        v = d[name]
+        if name == "bc_y" and isinstance(v, str):
+            v = BC[v]
+        if name == "flow" and isinstance(v, str):
+            v = FLOW[v]
+        setattr(p, name, v)
+    return p
+
+
+class Context:
+    """A set of simulations advanced together by the HIP library.
+
+    ``params``: list of dicts keyed by ``cmlb_sim_params`` names (strings
+    accepted for ``bc_y`` and ``flow``).  ``stream``: a hipStream_t handle
+    as an int (e.g. ``torch.cuda.current_stream().cuda_stream``) or None.
+    """
+
+    def __init__(self, params, precision="fp64", stream=None):
+        if isinstance(params, dict):
+            params = [params]
+        self.L = load()
+        self.params = [dict(p) for p in params]
+        arr = (SimParams * len(params))(*[make_params(p) for p in params])
+        self._arr = arr
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.precision = prec
+        h = ctypes.c_void_p()
+        rc = self.L.cmlb_create(arr, len(params), prec, ctypes.c_void_p(stream or 0),
+                                ctypes.byref(h))
+        if rc != OK:
+            raise CmlbError(rc, "cmlb_create failed")
+        self.h = h
+        self.shapes = [(int(p["ny"]), int(p["nx"])) for p in self.params]
+        fl = self.params[0].get("flow", 0)
+        self.coupled = (FLOW[fl] if isinstance(fl, str) else fl) == 2
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self.L.cmlb_last_error(self.h)
+            raise CmlbError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cmlb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def init_fields(self, sim, phi, c, ux=None, uy=None, P=None):
+        sh = self.shapes[sim]
+        arrs = [_f64(v, sh) for v in (phi, c, ux, uy, P)]
+        self._check(self.L.cmlb_init_fields(self.h, sim, *[_dptr(a) for a in arrs]),
+                    "cmlb_init_fields")
+
+    def step(self, n=1):
+        self._check(self.L.cmlb_step(self.h, int(n)), "cmlb_step")
+
+    def read_fields(self, sim=0):
+        sh = self.shapes[sim]
+        out = {k: np.zeros(sh) for k in ("phi", "c", "ux", "uy", "P")}
+        self._check(self.L.cmlb_read_fields(self.h, sim, _dptr(out["phi"]), _dptr(out["c"]),
+                                            _dptr(out["ux"]), _dptr(out["uy"]),
+                                            _dptr(out["P"])), "cmlb_read_fields")
+        return out
+
+    def inventory(self, sim=0):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.cmlb_inventory(self.h, sim, ctypes.byref(a), ctypes.byref(b)),
+                    "cmlb_inventory")
+        return a.value, b.value
+
+    def get_populations(self, sim=0):
+        ny, nx = self.shapes[sim]
+        f = np.zeros((9, ny, nx))
+        h = np.zeros((9, ny, nx))
+        g = np.zeros((9, ny, nx)) if self.coupled else None
+        self._check(self.L.cmlb_get_populations(self.h, sim, _dptr(f), _dptr(h), _dptr(g)),
+                    "cmlb_get_populations")
+        return f, h, g
+
+    def set_populations(self, sim, f, h, g=None):
+        ny, nx = self.shapes[sim]
+        f = _f64(f, (9, ny, nx))
+        h = _f64(h, (9, ny, nx))
+        g = _f64(g, (9, ny, nx)) if g is not None else None
+        self._check(self.L.cmlb_set_populations(self.h, sim, _dptr(f), _dptr(h), _dptr(g)),
+                    "cmlb_set_populations")
+
+    def set_step_count(self, n):
+        self._check(self.L.cmlb_set_step_count(self.h, int(n)), "cmlb_set_step_count")
+
+    def fault_flags(self, sim=0):
+        v = ctypes.c_int32()
+        self._check(self.L.cmlb_fault_flags(self.h, sim, ctypes.byref(v)), "cmlb_fault_flags")
+        return v.value
+
+    def synchronize(self):
+        self._check(self.L.cmlb_synchronize(self.h), "cmlb_synchronize")
+
+    def set_tile_rows(self, rows):
+        self._check(self.L.cmlb_set_tile_rows(self.h, int(rows)), "cmlb_set_tile_rows")
+
+    def launch_options(self):
+        buf = (ctypes.c_int32 * 16)()
+        n = self.L.cmlb_launch_options(self.h, buf, 16)
+        return [buf[i] for i in range(max(n, 0))]
+
+    def set_use_graph(self, on):
+        self._check(self.L.cmlb_set_use_graph(self.h, 1 if on else 0), "cmlb_set_use_graph")
+
+    @property
+    def step_count(self):
+        return self.L.cmlb_step_count(self.h)

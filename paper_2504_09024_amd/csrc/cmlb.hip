@@ -1,0 +1,635 @@
+// Host runtime and C ABI (include/cmlb.h) of the MI355X coupled
+// central-moment LB step.  Owns device buffers, the tile tables, the step
+// counter and the HIP graphs; every step runs in the kernels of kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cmlb.h"
+#include "kernels.hpp"
+
+using namespace cmlb;
+
+namespace {
+
+constexpr int GRAPH_PAIRS = 8;  // a graph holds 2 * GRAPH_PAIRS steps
+
+size_t storage_bytes(int prec) { return prec == CMLB_FP64 ? 8 : (prec == CMLB_FP32 ? 4 : 2); }
+
+double omega_of(double coeff) { return 1.0 / (coeff * 3.0 + 0.5); }
+
+bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
+
+double pow2_floor(double v) { return std::ldexp(1.0, (int)std::floor(std::log2(v))); }
+
+}  // namespace
+
+struct cmlb_ctx {
+    int n_sims = 0;
+    int prec = 0;
+    int flow = 0;
+    int walls = 0;
+    int nlat = 2;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    std::vector<cmlb_sim_params> params;
+    std::vector<SimDev> sims;
+    std::vector<char> inited;
+    int64_t pop_elems = 0;
+    int64_t ushape_elems = 0;
+    int64_t max_plane = 0;
+    int max_ny = 0;
+    void* pop[2] = {nullptr, nullptr};
+    void* ushape = nullptr;
+    SimDev* d_sims = nullptr;
+    int4* d_tiles = nullptr;
+    int ntiles = 0;
+    int64_t* d_step = nullptr;  // [2]
+    int32_t* d_fault = nullptr; // [n_sims]
+    double* d_stage = nullptr;  // staging: max(27, 5) * max_plane doubles
+    double* d_rows = nullptr;   // inventory row partials
+    double* d_inv = nullptr;    // [2]
+    int cur = 0;                // population/counter parity holding the current state
+    int64_t step = 0;
+    int tile_rows = 0;          // 0 = default
+    int use_graph = 1;
+    bool fault_seen = false;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+int fail(cmlb_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), CMLB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int default_rows(int prec) { return prec == CMLB_FP64 ? 8 : 16; }
+
+bool rows_ok(int prec, int rows) {
+    if (prec == CMLB_FP64) return rows == 4 || rows == 8;
+    return rows == 4 || rows == 8 || rows == 16;
+}
+
+// ------------------------------------------------------------------------
+// kernel selection
+// ------------------------------------------------------------------------
+using StepFn = void (*)(StepArgs);
+
+template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
+StepFn pick_npt(int npt) {
+    switch (npt) {
+        case 1: return k_step<S, T, FLOW, WALLS, 1, FIELDS>;
+        case 2: return k_step<S, T, FLOW, WALLS, 2, FIELDS>;
+        default: return k_step<S, T, FLOW, WALLS, 4, FIELDS>;
+    }
+}
+template <class S, class T, bool FIELDS>
+StepFn pick_flow(int flow, int walls, int npt) {
+    if (flow == FLOW_NONE)
+        return walls ? pick_npt<S, T, FLOW_NONE, true, FIELDS>(npt)
+                     : pick_npt<S, T, FLOW_NONE, false, FIELDS>(npt);
+    if (flow == FLOW_PRESCRIBED)
+        return walls ? pick_npt<S, T, FLOW_PRESCRIBED, true, FIELDS>(npt)
+                     : pick_npt<S, T, FLOW_PRESCRIBED, false, FIELDS>(npt);
+    return walls ? pick_npt<S, T, FLOW_COUPLED, true, FIELDS>(npt)
+                 : pick_npt<S, T, FLOW_COUPLED, false, FIELDS>(npt);
+}
+StepFn pick_step(int prec, int flow, int walls, int rows, bool fields) {
+    const int npt = rows / 4;
+    if (prec == CMLB_FP64)
+        return fields ? pick_flow<double, double, true>(flow, walls, npt)
+                      : pick_flow<double, double, false>(flow, walls, npt);
+    if (prec == CMLB_FP32)
+        return fields ? pick_flow<float, float, true>(flow, walls, npt)
+                      : pick_flow<float, float, false>(flow, walls, npt);
+    return fields ? pick_flow<_Float16, float, true>(flow, walls, npt)
+                  : pick_flow<_Float16, float, false>(flow, walls, npt);
+}
+
+int rows_of(const cmlb_ctx* c) { return c->tile_rows ? c->tile_rows : default_rows(c->prec); }
+
+void drop_graphs(cmlb_ctx* c) {
+    for (int i = 0; i < 2; ++i) {
+        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+        c->gexec[i] = nullptr;
+        c->graph[i] = nullptr;
+    }
+}
+
+int build_tiles(cmlb_ctx* c) {
+    const int rows = rows_of(c);
+    std::vector<int4> tiles;
+    for (int s = 0; s < c->n_sims; ++s) {
+        SimDev& d = c->sims[s];
+        d.tile0 = (int)tiles.size();
+        for (int y0 = 0; y0 < d.ny; y0 += rows)
+            for (int x0 = 0; x0 < d.nx; x0 += TX) tiles.push_back(make_int4(s, x0, y0, 0));
+        d.ntiles = (int)tiles.size() - d.tile0;
+    }
+    if (c->d_tiles) (void)hipFree(c->d_tiles);
+    c->d_tiles = nullptr;
+    c->ntiles = (int)tiles.size();
+    HIP_TRY(c, hipMalloc(&c->d_tiles, sizeof(int4) * tiles.size()));
+    HIP_TRY(c, hipMemcpy(c->d_tiles, tiles.data(), sizeof(int4) * tiles.size(),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->d_sims, c->sims.data(), sizeof(SimDev) * c->sims.size(),
+                         hipMemcpyHostToDevice));
+    drop_graphs(c);
+    return CMLB_OK;
+}
+
+StepArgs step_args(cmlb_ctx* c, int parity) {
+    StepArgs a;
+    memset(&a, 0, sizeof(a));
+    a.src = c->pop[parity];
+    a.dst = c->pop[parity ^ 1];
+    a.sims = c->d_sims;
+    a.tiles = c->d_tiles;
+    a.tile_base = 0;
+    a.ushape = c->ushape;
+    a.step_in = c->d_step + parity;
+    a.step_out = c->d_step + (parity ^ 1);
+    a.fault = c->d_fault;
+    a.fields_out = nullptr;
+    return a;
+}
+
+int launch_step(cmlb_ctx* c, int parity) {
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, rows_of(c), false);
+    StepArgs a = step_args(c, parity);
+    hipLaunchKernelGGL(fn, dim3(c->ntiles), dim3(WG), 0, c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+    return CMLB_OK;
+}
+
+// Graph of 2*GRAPH_PAIRS steps starting from parity p (ends at parity p).
+int build_graph(cmlb_ctx* c, int p) {
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, rows_of(c), false);
+    HIP_TRY(c, hipGraphCreate(&c->graph[p], 0));
+    hipGraphNode_t prev = nullptr;
+    for (int k = 0; k < 2 * GRAPH_PAIRS; ++k) {
+        StepArgs a = step_args(c, p ^ (k & 1));
+        void* kargs[] = {&a};
+        hipKernelNodeParams np;
+        memset(&np, 0, sizeof(np));
+        np.func = reinterpret_cast<void*>(fn);
+        np.gridDim = dim3(c->ntiles);
+        np.blockDim = dim3(WG);
+        np.sharedMemBytes = 0;
+        np.kernelParams = kargs;
+        np.extra = nullptr;
+        hipGraphNode_t node;
+        HIP_TRY(c, hipGraphAddKernelNode(&node, c->graph[p], prev ? &prev : nullptr, prev ? 1 : 0,
+                                         &np));
+        prev = node;
+    }
+    HIP_TRY(c, hipGraphInstantiate(&c->gexec[p], c->graph[p], nullptr, nullptr, 0));
+    return CMLB_OK;
+}
+
+int check_sim(const cmlb_ctx* c, int sim) { return sim >= 0 && sim < c->n_sims; }
+
+int sync_and_check(cmlb_ctx* c) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<int32_t> f(c->n_sims);
+    HIP_TRY(c, hipMemcpy(f.data(), c->d_fault, sizeof(int32_t) * c->n_sims, hipMemcpyDeviceToHost));
+    for (int s = 0; s < c->n_sims; ++s)
+        if (f[s]) {
+            c->fault_seen = true;
+            return fail(c, CMLB_ERANGE, "fault flags 0x%x raised in simulation %d", f[s], s);
+        }
+    return CMLB_OK;
+}
+
+template <class S>
+void launch_decode(cmlb_ctx* c, int sim) {
+    const SimDev& d = c->sims[sim];
+    const int64_t total = (int64_t)c->nlat * 9 * d.nx * d.ny;
+    const char* base = static_cast<const char*>(c->pop[c->cur]) + d.off * (int64_t)sizeof(S);
+    hipLaunchKernelGGL(k_decode<S>, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0,
+                       c->stream, (const void*)base, (const SimDev*)(c->d_sims + sim), c->nlat,
+                       c->d_stage);
+}
+template <class S>
+void launch_encode(cmlb_ctx* c, int sim) {
+    const SimDev& d = c->sims[sim];
+    const int64_t total = (int64_t)c->nlat * 9 * d.nx * d.ny;
+    char* base = static_cast<char*>(c->pop[c->cur]) + d.off * (int64_t)sizeof(S);
+    hipLaunchKernelGGL(k_encode<S>, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0,
+                       c->stream, (void*)base, (const SimDev*)(c->d_sims + sim), c->nlat,
+                       (const double*)c->d_stage);
+}
+template <class S>
+void launch_inventory(cmlb_ctx* c, int sim) {
+    const SimDev& d = c->sims[sim];
+    const char* base = static_cast<const char*>(c->pop[c->cur]) + d.off * (int64_t)sizeof(S);
+    hipLaunchKernelGGL(k_inventory_rows<S>, dim3(d.ny), dim3(WG), 0, c->stream,
+                       (const void*)base, (const SimDev*)(c->d_sims + sim), c->d_rows);
+    hipLaunchKernelGGL(k_inventory_final, dim3(1), dim3(64), 0, c->stream,
+                       (const double*)c->d_rows, d.ny, c->d_inv);
+}
+template <class S, class T>
+void launch_init(cmlb_ctx* c, int sim, const InitArgs& a) {
+    const SimDev& d = c->sims[sim];
+    const int plane = d.nx * d.ny;
+    hipLaunchKernelGGL((k_init<S, T>), dim3((plane + WG - 1) / WG), dim3(WG), 0, c->stream, a);
+}
+
+void release(cmlb_ctx* c) {
+    drop_graphs(c);
+    (void)hipFree(c->pop[0]);
+    (void)hipFree(c->pop[1]);
+    (void)hipFree(c->ushape);
+    (void)hipFree(c->d_sims);
+    (void)hipFree(c->d_tiles);
+    (void)hipFree(c->d_step);
+    (void)hipFree(c->d_fault);
+    (void)hipFree(c->d_stage);
+    (void)hipFree(c->d_rows);
+    (void)hipFree(c->d_inv);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision,
+                void* hip_stream, cmlb_ctx** out) {
+    if (!out) return CMLB_EINVAL;
+    *out = nullptr;
+    if (!params || n_sims < 1) return CMLB_EINVAL;
+    if (precision < CMLB_FP64 || precision > CMLB_FP16) return CMLB_EINVAL;
+    const int flow = params[0].flow, bc = params[0].bc_y;
+    if (flow < CMLB_FLOW_NONE || flow > CMLB_FLOW_COUPLED) return CMLB_EINVAL;
+    if (bc != CMLB_BC_PERIODIC && bc != CMLB_BC_MOVING_WALLS) return CMLB_EINVAL;
+    const int nlat = flow == CMLB_FLOW_COUPLED ? 3 : 2;
+    std::vector<SimDev> sims(n_sims);
+    int64_t off = 0, uoff = 0, max_plane = 0;
+    int max_ny = 0;
+    for (int s = 0; s < n_sims; ++s) {
+        const cmlb_sim_params& p = params[s];
+        if (p.flow != flow || p.bc_y != bc) return CMLB_EINVAL;
+        if (p.nx < 4 || p.ny < 4) return CMLB_EINVAL;
+        const int64_t plane = (int64_t)p.nx * p.ny;
+        if (plane * 27 >= (int64_t)INT32_MAX) return CMLB_EINVAL;
+        if (!(p.W > 0.0) || !(p.phi_a != p.phi_b) || !std::isfinite(p.phi_a) ||
+            !std::isfinite(p.phi_b))
+            return CMLB_EINVAL;
+        if (!(p.M_phi >= 0.0) || !(p.D_s >= 0.0)) return CMLB_EINVAL;
+        const double wk = omega_of(p.M_phi), wc = omega_of(p.D_s);
+        if (!rate_ok(wk) || !rate_ok(wc)) return CMLB_EUNSTABLE;
+        SimDev d;
+        memset(&d, 0, sizeof(d));
+        d.nx = p.nx;
+        d.ny = p.ny;
+        d.off = off;
+        d.ushape_off = uoff;
+        d.W = p.W;
+        d.phi_a = p.phi_a;
+        d.phi_b = p.phi_b;
+        d.inv_dphi = 1.0 / (p.phi_a - p.phi_b);
+        d.phim = 0.5 * (p.phi_a + p.phi_b);
+        d.theta_k = 4.0 / p.W;
+        d.thetac_k = 8.0 / p.W;
+        d.M_phi = p.M_phi;
+        d.D_s = p.D_s;
+        d.omega_k = wk;
+        d.omega_c = wc;
+        d.rho_b = p.rho_b;
+        d.drho = p.rho_a - p.rho_b;
+        d.nu_b = p.nu_b;
+        d.dnu = p.nu_a - p.nu_b;
+        d.omega_zeta = p.omega_zeta;
+        d.sigma0 = p.sigma0;
+        d.beta = p.beta;
+        d.c_max = p.c_max;
+        const double phio = 0.5 * (p.phi_a - p.phi_b);
+        d.ks = 3.0 * p.W / (8.0 * phio * phio);
+        d.u_wall = bc == CMLB_BC_MOVING_WALLS ? p.u_wall : 0.0;
+        d.F_ext_x = p.F_ext_x;
+        d.F_ext_y = p.F_ext_y;
+        d.vel_period_T = p.vel_period_T;
+        d.P_ref = p.rho_b / 3.0;
+        if (flow == CMLB_FLOW_COUPLED) {
+            if (!(p.rho_a > 0.0) || !(p.rho_b > 0.0) || !(p.c_max > 0.0)) return CMLB_EINVAL;
+            if (!(p.nu_a >= 0.0) || !(p.nu_b >= 0.0)) return CMLB_EINVAL;
+            if (!rate_ok(omega_of(p.nu_a)) || !rate_ok(omega_of(p.nu_b)) || !rate_ok(p.omega_zeta))
+                return CMLB_EUNSTABLE;
+        }
+        if (precision == CMLB_FP16) {
+            // f: deviation from phi_m, bulk values map to +-1/2 exactly
+            d.qref_f = d.phim;
+            d.scale_f = 0.5 / pow2_floor(std::fabs(phio) * 1.0000001);
+            if (!(d.scale_f > 0.0) || !std::isfinite(d.scale_f)) d.scale_f = 1.0;
+            d.scale_h = 16.0 / pow2_floor(p.c_max > 0.0 ? p.c_max : 1.0);
+            const double uref = std::max(std::fabs(d.u_wall), 1e-4);
+            d.scale_g = pow2_floor(32.0 / (3.0 * uref));
+        } else {
+            d.qref_f = 0.0;
+            d.scale_f = d.scale_h = d.scale_g = 1.0;
+        }
+        sims[s] = d;
+        off += (int64_t)nlat * 9 * plane;
+        if (flow == CMLB_FLOW_PRESCRIBED) uoff += 2 * plane;
+        max_plane = std::max(max_plane, plane);
+        max_ny = std::max(max_ny, p.ny);
+    }
+
+    cmlb_ctx* c = new (std::nothrow) cmlb_ctx();
+    if (!c) return CMLB_ENOMEM;
+    c->n_sims = n_sims;
+    c->prec = precision;
+    c->flow = flow;
+    c->walls = bc == CMLB_BC_MOVING_WALLS;
+    c->nlat = nlat;
+    c->params.assign(params, params + n_sims);
+    c->sims = sims;
+    c->inited.assign(n_sims, 0);
+    c->pop_elems = off;
+    c->ushape_elems = uoff;
+    c->max_plane = max_plane;
+    c->max_ny = max_ny;
+    auto bail = [&](int code) {
+        release(c);
+        delete c;
+        return code;
+    };
+    if (hipGetDevice(&c->device) != hipSuccess) return bail(CMLB_EDEVICE);
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(CMLB_EDEVICE);
+        c->own_stream = true;
+    }
+    const size_t sb = storage_bytes(precision);
+    const size_t tb = precision == CMLB_FP64 ? 8 : 4;
+    if (hipMalloc(&c->pop[0], sb * off) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->pop[1], sb * off) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (uoff && hipMalloc(&c->ushape, tb * uoff) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_sims, sizeof(SimDev) * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_step, sizeof(int64_t) * 2) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_fault, sizeof(int32_t) * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_stage, sizeof(double) * 27 * max_plane) != hipSuccess)
+        return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_rows, sizeof(double) * 2 * max_ny) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_inv, sizeof(double) * 2) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMemset(c->pop[0], 0, sb * off) != hipSuccess) return bail(CMLB_EDEVICE);
+    if (hipMemset(c->pop[1], 0, sb * off) != hipSuccess) return bail(CMLB_EDEVICE);
+    if (hipMemset(c->d_step, 0, sizeof(int64_t) * 2) != hipSuccess) return bail(CMLB_EDEVICE);
+    if (hipMemset(c->d_fault, 0, sizeof(int32_t) * n_sims) != hipSuccess) return bail(CMLB_EDEVICE);
+    if (build_tiles(c) != CMLB_OK) return bail(CMLB_EDEVICE);
+    *out = c;
+    return CMLB_OK;
+}
+
+int cmlb_init_fields(cmlb_ctx* c, int32_t sim, const double* phi, const double* cc,
+                     const double* ux, const double* uy, const double* p) {
+    if (!c) return CMLB_EINVAL;
+    if (!check_sim(c, sim) || !phi || !cc) return fail(c, CMLB_EINVAL, "bad simulation or field");
+    const SimDev& d = c->sims[sim];
+    const int64_t plane = (int64_t)d.nx * d.ny;
+    double* st = c->d_stage;
+    // staging layout: phi, c, ux, uy, P
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(st, phi, sizeof(double) * plane, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(st + plane, cc, sizeof(double) * plane, hipMemcpyHostToDevice));
+    if (ux) HIP_TRY(c, hipMemcpy(st + 2 * plane, ux, sizeof(double) * plane, hipMemcpyHostToDevice));
+    if (uy) HIP_TRY(c, hipMemcpy(st + 3 * plane, uy, sizeof(double) * plane, hipMemcpyHostToDevice));
+    if (p) HIP_TRY(c, hipMemcpy(st + 4 * plane, p, sizeof(double) * plane, hipMemcpyHostToDevice));
+    InitArgs a;
+    memset(&a, 0, sizeof(a));
+    a.sd = c->d_sims + sim;
+    a.phi = st;
+    a.c = st + plane;
+    a.ux = ux ? st + 2 * plane : nullptr;
+    a.uy = uy ? st + 3 * plane : nullptr;
+    a.P = p ? st + 4 * plane : nullptr;
+    a.flow = c->flow;
+    a.walls = c->walls;
+    const size_t tb = c->prec == CMLB_FP64 ? 8 : 4;
+    a.ushape = c->flow == CMLB_FLOW_PRESCRIBED ? static_cast<char*>(c->ushape) + d.ushape_off * tb
+                                               : nullptr;
+    // initialise both copies' parity: write into the current buffer
+    const size_t sb = storage_bytes(c->prec);
+    a.pop = static_cast<char*>(c->pop[c->cur]) + d.off * sb;
+    if (c->prec == CMLB_FP64)
+        launch_init<double, double>(c, sim, a);
+    else if (c->prec == CMLB_FP32)
+        launch_init<float, float>(c, sim, a);
+    else
+        launch_init<_Float16, float>(c, sim, a);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->inited[sim] = 1;
+    c->step = 0;
+    int64_t zero[2] = {0, 0};
+    HIP_TRY(c, hipMemcpy(c->d_step, zero, sizeof(zero), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemset(c->d_fault + sim, 0, sizeof(int32_t)));
+    return CMLB_OK;
+}
+
+int cmlb_step(cmlb_ctx* c, int32_t n) {
+    if (!c) return CMLB_EINVAL;
+    if (n < 0) return fail(c, CMLB_EINVAL, "negative step count");
+    for (int s = 0; s < c->n_sims; ++s)
+        if (!c->inited[s]) return fail(c, CMLB_ESTATE, "simulation %d not initialised", s);
+    if (c->fault_seen) return fail(c, CMLB_ERANGE, "a fault flag was raised earlier");
+    int left = n;
+    if (c->use_graph) {
+        const int per = 2 * GRAPH_PAIRS;
+        while (left >= per) {
+            const int p = c->cur;
+            if (!c->gexec[p]) {
+                int rc = build_graph(c, p);
+                if (rc != CMLB_OK) return rc;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->gexec[p], c->stream));
+            left -= per;
+            c->step += per;
+        }
+    }
+    while (left > 0) {
+        int rc = launch_step(c, c->cur);
+        if (rc != CMLB_OK) return rc;
+        c->cur ^= 1;
+        c->step += 1;
+        --left;
+    }
+    return CMLB_OK;
+}
+
+int cmlb_read_fields(cmlb_ctx* c, int32_t sim, double* phi, double* cc, double* ux, double* uy,
+                     double* p) {
+    if (!c) return CMLB_EINVAL;
+    if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
+    const SimDev& d = c->sims[sim];
+    const int64_t plane = (int64_t)d.nx * d.ny;
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, rows_of(c), true);
+    StepArgs a = step_args(c, c->cur);
+    a.dst = nullptr;
+    a.step_out = nullptr;
+    a.tile_base = d.tile0;
+    a.fields_out = c->d_stage;
+    hipLaunchKernelGGL(fn, dim3(d.ntiles), dim3(WG), 0, c->stream, a);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double* outs[5] = {phi, cc, ux, uy, p};
+    for (int f = 0; f < 5; ++f)
+        if (outs[f])
+            HIP_TRY(c, hipMemcpy(outs[f], c->d_stage + f * plane, sizeof(double) * plane,
+                                 hipMemcpyDeviceToHost));
+    return sync_and_check(c);
+}
+
+int cmlb_inventory(cmlb_ctx* c, int32_t sim, double* sum_phi, double* sum_c) {
+    if (!c) return CMLB_EINVAL;
+    if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
+    if (c->prec == CMLB_FP64)
+        launch_inventory<double>(c, sim);
+    else if (c->prec == CMLB_FP32)
+        launch_inventory<float>(c, sim);
+    else
+        launch_inventory<_Float16>(c, sim);
+    HIP_TRY(c, hipGetLastError());
+    double v[2];
+    HIP_TRY(c, hipMemcpyAsync(v, c->d_inv, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (sum_phi) *sum_phi = v[0];
+    if (sum_c) *sum_c = v[1];
+    return CMLB_OK;
+}
+
+int cmlb_get_populations(cmlb_ctx* c, int32_t sim, double* f, double* h, double* g) {
+    if (!c) return CMLB_EINVAL;
+    if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
+    const SimDev& d = c->sims[sim];
+    const int64_t plane = (int64_t)d.nx * d.ny;
+    if (c->prec == CMLB_FP64)
+        launch_decode<double>(c, sim);
+    else if (c->prec == CMLB_FP32)
+        launch_decode<float>(c, sim);
+    else
+        launch_decode<_Float16>(c, sim);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double* outs[3] = {f, h, g};
+    for (int l = 0; l < c->nlat; ++l)
+        if (outs[l])
+            HIP_TRY(c, hipMemcpy(outs[l], c->d_stage + (int64_t)l * 9 * plane,
+                                 sizeof(double) * 9 * plane, hipMemcpyDeviceToHost));
+    return CMLB_OK;
+}
+
+int cmlb_set_populations(cmlb_ctx* c, int32_t sim, const double* f, const double* h,
+                         const double* g) {
+    if (!c) return CMLB_EINVAL;
+    if (!check_sim(c, sim) || !f || !h || (c->nlat == 3 && !g))
+        return fail(c, CMLB_EINVAL, "bad simulation index or population array");
+    const SimDev& d = c->sims[sim];
+    const int64_t plane = (int64_t)d.nx * d.ny;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double* ins[3] = {f, h, g};
+    for (int l = 0; l < c->nlat; ++l)
+        HIP_TRY(c, hipMemcpy(c->d_stage + (int64_t)l * 9 * plane, ins[l], sizeof(double) * 9 * plane,
+                             hipMemcpyHostToDevice));
+    if (c->prec == CMLB_FP64)
+        launch_encode<double>(c, sim);
+    else if (c->prec == CMLB_FP32)
+        launch_encode<float>(c, sim);
+    else
+        launch_encode<_Float16>(c, sim);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->inited[sim] = 1;
+    return CMLB_OK;
+}
+
+int cmlb_set_step_count(cmlb_ctx* c, int64_t step) {
+    if (!c || step < 0) return CMLB_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int64_t v[2] = {step, step};
+    HIP_TRY(c, hipMemcpy(c->d_step, v, sizeof(v), hipMemcpyHostToDevice));
+    c->step = step;
+    return CMLB_OK;
+}
+
+int cmlb_fault_flags(cmlb_ctx* c, int32_t sim, int32_t* flags) {
+    if (!c || !flags) return CMLB_EINVAL;
+    if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(flags, c->d_fault + sim, sizeof(int32_t), hipMemcpyDeviceToHost));
+    return CMLB_OK;
+}
+
+int cmlb_synchronize(cmlb_ctx* c) {
+    if (!c) return CMLB_EINVAL;
+    return sync_and_check(c);
+}
+
+int cmlb_set_tile_rows(cmlb_ctx* c, int32_t rows) {
+    if (!c) return CMLB_EINVAL;
+    if (rows != 0 && !rows_ok(c->prec, rows))
+        return fail(c, CMLB_EINVAL, "tile rows %d not supported", rows);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->tile_rows = rows;
+    return build_tiles(c);
+}
+
+int cmlb_launch_options(const cmlb_ctx* c, int32_t* rows, int32_t cap) {
+    if (!c || (!rows && cap > 0)) return CMLB_EINVAL;
+    const int opts64[] = {4, 8};
+    const int opts32[] = {4, 8, 16};
+    const int* o = c->prec == CMLB_FP64 ? opts64 : opts32;
+    const int n = c->prec == CMLB_FP64 ? 2 : 3;
+    for (int i = 0; i < n && i < cap; ++i) rows[i] = o[i];
+    return n;
+}
+
+int cmlb_set_use_graph(cmlb_ctx* c, int32_t on) {
+    if (!c) return CMLB_EINVAL;
+    c->use_graph = on ? 1 : 0;
+    return CMLB_OK;
+}
+
+int64_t cmlb_step_count(const cmlb_ctx* c) { return c ? c->step : -1; }
+int32_t cmlb_num_sims(const cmlb_ctx* c) { return c ? c->n_sims : 0; }
+const char* cmlb_last_error(const cmlb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void cmlb_destroy(cmlb_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+}  // extern "C"

@@ -69,12 +69,14 @@ def drop_fields(nx, ny, xc, yc, R, W, c_hat=None, phi_a=1.0, phi_b=0.0, y_offset
 # Named workloads
 # ---------------------------------------------------------------------------
 
-def static_drop(n=128, R=32.0, W=4.0, D_s=0.01, M_phi=0.1, mode=1):
+def static_drop(n=128, R=32.0, W=4.0, D_s=0.01, M_phi=0.1, mode=1, center=None):
     """Static drop with a cos(mode*theta) surfactant gradient, u = 0
     (Sec. 4.1 set-up, scaled: 128x128 periodic, R = 32, W = 4, D_s = 0.01).
-    c_hat = (1 - cos(mode theta))/2."""
+    c_hat = (1 - cos(mode theta))/2.  The centre defaults to the node
+    (n/2, n/2)."""
     p = params(nx=n, ny=n, bc_y="periodic", flow="none", W=W, D_s=D_s, M_phi=M_phi)
-    phi, c = drop_fields(n, n, n / 2, n / 2, R, W, lambda th: 0.5 * (1.0 - np.cos(mode * th)))
+    xc, yc = center if center is not None else (n / 2, n / 2)
+    phi, c = drop_fields(n, n, xc, yc, R, W, lambda th: 0.5 * (1.0 - np.cos(mode * th)))
     return p, dict(phi=phi, c=c)
 
 
@@ -168,21 +170,37 @@ def flat_interface(nx=64, ny=8, W=4.0, c_hat=0.0, M_phi=0.1, D_s=0.05):
                    c=np.ascontiguousarray(np.broadcast_to(c, (ny, nx))))
 
 
+def _smooth_noise(rng, nx, ny, modes=4, periodic_y=True):
+    """Sum of a few random low-wavenumber Fourier modes, unit RMS-ish."""
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    out = np.zeros((ny, nx))
+    for _ in range(modes):
+        kx = int(rng.integers(1, 4))
+        ky = int(rng.integers(1, 4))
+        ph = rng.uniform(0, 2 * np.pi, 2)
+        ly = ny if periodic_y else 2 * ny
+        out += np.cos(2 * np.pi * kx * x / nx + ph[0]) * np.cos(2 * np.pi * ky * y / ly + ph[1])
+    return out / np.sqrt(modes)
+
+
 def random_fields(nx, ny, seed=0, flow="coupled", bc_y="walls", amp=0.05, **kw):
-    """Smooth random fields (for parity tests): a drop plus low-amplitude
-    seeded noise on phi, c and u."""
+    """Seeded smooth random fields for parity tests: an off-node drop with an
+    angle-dependent surfactant load, plus low-wavenumber random perturbations
+    of phi, c, u and P (smooth, so the case stays well conditioned)."""
     rng = np.random.default_rng(seed)
     p = params(nx=nx, ny=ny, bc_y=bc_y, flow=flow, **kw)
     R = min(nx, ny) / 4.0
     y_off = 0.5 if bc_y == "walls" else 0.0
+    per = bc_y != "walls"
     phi, c = drop_fields(nx, ny, nx / 2.0 + 0.3, ny / 2.0 - 0.2, R, p["W"],
                          lambda th: 0.2 + 0.1 * np.cos(th) + 0.05 * np.sin(3 * th),
                          y_offset=y_off)
-    phi = phi + amp * 0.1 * rng.standard_normal(phi.shape)
-    c = np.abs(c + amp * 0.02 * rng.standard_normal(c.shape))
-    ux = amp * 0.01 * rng.standard_normal(phi.shape)
-    uy = amp * 0.01 * rng.standard_normal(phi.shape)
-    P = CS2 + amp * 1e-3 * rng.standard_normal(phi.shape)
+    phi = phi + amp * 0.1 * _smooth_noise(rng, nx, ny, periodic_y=per)
+    c = c * (1.0 + amp * _smooth_noise(rng, nx, ny, periodic_y=per))
+    ux = amp * 0.01 * _smooth_noise(rng, nx, ny, periodic_y=per)
+    uy = amp * 0.01 * _smooth_noise(rng, nx, ny, periodic_y=per)
+    P = CS2 + amp * 1e-3 * _smooth_noise(rng, nx, ny, periodic_y=per)
     return p, dict(phi=np.ascontiguousarray(phi), c=np.ascontiguousarray(c),
                    ux=np.ascontiguousarray(ux), uy=np.ascontiguousarray(uy),
                    P=np.ascontiguousarray(P))

@@ -1,0 +1,39 @@
+"""Named parity cases shared by the GPU parity tests and the CPU check of
+their conditioning.  Each entry: builder() -> (params, fields), steps."""
+import numpy as np
+
+from paper_2504_09024_amd import workloads as W
+
+
+def _ragged():
+    p, _ = W.static_drop(n=100, R=24.0)
+    p = dict(p, ny=70)
+    phi, c = W.drop_fields(100, 70, 47.3, 36.1, 20.0, 4.0, lambda t: 0.5 * (1 - np.cos(t)))
+    return p, dict(phi=phi, c=c)
+
+
+CASES = {
+    # static drop of Sec. 4.1 at the 128x128 scale, all 2000 steps
+    "c1_static_drop": (lambda: W.static_drop(), 2000),
+    "ragged_periodic": (_ragged, 300),
+    "vortex": (lambda: W.vortex_drop(n=96, R=16.0, U0=0.02, T=400.0, center=(48.3, 63.7)), 400),
+    # Re = 1 shear drop (the inertial set-up of Sec. 4.3, scaled): u ~ 1e-2,
+    # so the oracle's own rounding on O(1) populations stays far below 1e-12
+    # relative to u
+    "shear_drop": (lambda: W.shear_drop(nx=200, ny=72, R=12.0, Ca=0.35, E=0.25, c0=0.3,
+                                        Re=1.0), 200),
+    "coupled_random": (lambda: W.random_fields(136, 60, seed=3, amp=1.0, sigma0=2e-3,
+                                               beta=0.3, u_wall=2e-2, M_phi=0.04,
+                                               D_s=0.02), 150),
+    "density_ratio": (lambda: W.random_fields(96, 48, seed=5, amp=1.0, sigma0=1e-3, beta=0.2,
+                                              rho_a=2.0, rho_b=1.0, nu_a=0.05, nu_b=0.1,
+                                              omega_zeta=0.9, F_ext_x=1e-5, F_ext_y=-2e-5,
+                                              bc_y="periodic"), 150),
+    # 1024x512 coupled shear drop of the benchmark (Ca = 0.3, E = 0.2, c0 = 0.3)
+    "c3_full": (lambda: W.shear_drop(), 20),
+}
+
+# cases compared against the FP64 bar (1e-12) and cheap enough for the CPU
+# conditioning check
+FP64_CONDITIONING = ["ragged_periodic", "vortex", "shear_drop", "coupled_random",
+                     "density_ratio", "c3_full"]

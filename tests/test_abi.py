@@ -1,0 +1,95 @@
+"""The C ABI without a GPU: libcmlb.so loads, exports every function that
+include/cmlb.h declares, the parameter struct layout agrees between C and the
+binding, and argument validation happens before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmlb.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2504_09024_amd import build, cmlb
+    if build.is_stale():
+        build.build()
+    return cmlb.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmlb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_names():
+    from paper_2504_09024_amd import cmlb
+    assert declared_functions() == sorted(cmlb.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lib._name], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\s(cmlb_\w+)$", out, flags=re.M))
+    assert set(declared_functions()) <= exported
+
+
+def test_param_struct_layout_matches_c():
+    from paper_2504_09024_amd import cmlb
+    fields = [f for f, _ in cmlb.SimParams._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){",
+           'printf("%zu\\n", sizeof(cmlb_sim_params));']
+    src += [f'printf("%zu\\n", offsetof(cmlb_sim_params, {f}));' for f in fields]
+    src += ["return 0;}"]
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write("\n".join(src))
+        subprocess.run(["gcc", c, "-o", exe], check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                               check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(cmlb.SimParams)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(cmlb.SimParams, f).offset == off, f
+
+
+def _create(lib, plist, prec=0):
+    from paper_2504_09024_amd import cmlb
+    arr = (cmlb.SimParams * max(len(plist), 1))(*[cmlb.make_params(p) for p in plist])
+    h = ctypes.c_void_p()
+    rc = lib.cmlb_create(arr, len(plist), prec, None, ctypes.byref(h))
+    return rc, h
+
+
+def test_validation_before_device(lib):
+    from paper_2504_09024_amd import cmlb
+    from paper_2504_09024_amd import workloads as W
+    good = W.params(nx=64, ny=64)
+    assert _create(lib, [])[0] == cmlb.EINVAL
+    assert _create(lib, [dict(good, nx=2)])[0] == cmlb.EINVAL
+    assert _create(lib, [dict(good, phi_a=0.0, phi_b=0.0)])[0] == cmlb.EINVAL
+    assert _create(lib, [dict(good, W=0.0)])[0] == cmlb.EINVAL
+    assert _create(lib, [good], prec=7)[0] == cmlb.EINVAL
+    # sims of one context share flow and boundary type
+    assert _create(lib, [good, dict(good, flow="coupled")])[0] == cmlb.EINVAL
+    assert _create(lib, [good, dict(good, bc_y="walls")])[0] == cmlb.EINVAL
+    # relaxation rates outside (0, 2)
+    cpl = dict(good, flow="coupled")
+    assert _create(lib, [dict(cpl, omega_zeta=2.5)])[0] == cmlb.EUNSTABLE
+    assert _create(lib, [dict(cpl, nu_a=-0.2)])[0] in (cmlb.EINVAL, cmlb.EUNSTABLE)
+    assert _create(lib, [dict(good, M_phi=-0.1)])[0] == cmlb.EINVAL
+    # null output handle
+    arr = (cmlb.SimParams * 1)(cmlb.make_params(good))
+    assert lib.cmlb_create(arr, 1, 0, None, None) == cmlb.EINVAL
+    # null context everywhere
+    assert lib.cmlb_step(None, 1) == cmlb.EINVAL
+    assert lib.cmlb_step_count(None) == -1
+    assert lib.cmlb_last_error(None) == b"null context"
+    lib.cmlb_destroy(None)
