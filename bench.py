@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the coupled central-moment LB step on one MI355X.
 
-Default workload: the coupled surfactant-laden shear drop of Sec. 4.3 scaled
-to 1024 x 512 (R = 64, Ca = 0.3, E = 0.2, c0/c_max = 0.3, Re = 0.1), FP32
-storage and arithmetic.  A step is one collide-and-stream pass of all three
-lattices over every node; populations stay resident in HBM.  Prints one JSON
-line: coupled MLUPS, the dominant kernel's roofline fraction (algorithmic
-bytes over HIP-event-timed launches on the kernel's stream), the other
-storage forms and the batched form, and the CPU oracle timed on a bounded
-sample.
+Headline workload: 64 independent coupled surfactant-laden shear drops
+(Sec. 4.3 set-up) with seeded sizes from 256x256 to 1024x512 and seeded
+Ca, E, c0/c_max, Pe_s (numpy default_rng(2504)), advanced together by one
+launch per step; FP32 storage and arithmetic; 18.4 M nodes, 4 GB of
+populations (double-buffered), far above the 256 MB Infinity Cache, so HBM
+is the bound.  A step is one collide-and-stream pass of all three lattices
+over every node of every simulation; populations stay resident in HBM.
+
+Prints one JSON line: coupled MLUPS, the step kernel's roofline fraction
+(algorithmic bytes over HIP-event-timed launches on the kernel's stream),
+the other storage forms (FP64, FP16) of the batch and of the single
+1024x512 drop, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+                       [--workload batched|c3]
 """
 import argparse
 import hashlib
@@ -64,9 +69,13 @@ def timed_run(ctx, steps, warmup, torch):
     return start.elapsed_time(end) / 1e3, wall
 
 
-def make_ctx(cmlb, sims, prec, stream):
+def make_ctx(cmlb, sims, prec, stream, tile_rows=0, graph=True, xcd_remap=True):
     ps = [s[0] for s in sims]
     ctx = cmlb.Context(ps, prec, stream=stream)
+    if tile_rows:
+        ctx.set_tile_rows(tile_rows)
+    ctx.set_use_graph(graph)
+    ctx.set_xcd_remap(xcd_remap)
     for i, (_, fl) in enumerate(sims):
         ctx.init_fields(i, fl["phi"], fl["c"], fl.get("ux"), fl.get("uy"), fl.get("P"))
     return ctx
@@ -89,31 +98,59 @@ def traffic_entry(workload_key, prec):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(p, fl, steps):
+def cpu_baseline(sims, target_s=10.0):
+    """The FP64 oracle on a bounded sample of the workload: the first
+    simulation of the set, as many steps as fit ~target_s (at least 2)."""
     import oracle
+    p, fl = sims[0]
     o = oracle.OracleSim(oracle.make_params(**p), fl["phi"], fl["c"], fl.get("ux"),
                          fl.get("uy"), fl.get("P"))
     t0 = time.perf_counter()
-    o.run(steps)
+    o.run(2)
     dt = time.perf_counter() - t0
+    steps = 2
+    extra = max(0, int(target_s / max(dt / 2, 1e-6)) - 2)
+    extra = min(extra, 400)
+    if extra:
+        t1 = time.perf_counter()
+        o.run(extra)
+        dt += time.perf_counter() - t1
+        steps += extra
     nodes = p["nx"] * p["ny"]
-    return {"value": nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{steps} steps of the full {p['nx']}x{p['ny']} coupled grid "
-                      f"({dt:.1f} s, FP64, OpenMP over rows)"}
+    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} steps of simulation 0 of the workload ({p['nx']}x{p['ny']} "
+                      f"coupled, {dt:.1f} s, FP64, OpenMP over rows)"}
+
+
+def workload(W, name):
+    if name == "batched":
+        sims = W.batched_shear_drops(64)
+        desc = ("64 seeded coupled surfactant-laden shear drops (default_rng(2504)): sizes "
+                "256x256..1024x512, R=ny/8, Ca~U[0.05,0.6], E~U[0.1,0.5], c0~U[0.1,0.5], "
+                "Pe_s log-U[0.5,10], Re=0.1, Pe*=0.5, walls at +-U0; one launch per step")
+    else:
+        sims = [W.shear_drop()]
+        desc = ("coupled surfactant-laden shear drop, 1024x512, R=64, Ca=0.3, E=0.2, "
+                "c0/c_max=0.3, Re=0.1, walls at +-U0")
+    return sims, desc
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "c3"])
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-xcd-remap", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the other storage forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (the reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -133,14 +170,24 @@ def main():
     torch.cuda.set_stream(tstream)
     stream = tstream.cuda_stream
 
-    p, fl = W.shear_drop()
-    nodes = p["nx"] * p["ny"]
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
+                          "launches": 5}))
+        return
+
+    sims, desc = workload(W, args.workload)
+    nodes = sum(p["nx"] * p["ny"] for p, _ in sims)
     prec = args.precision
-    log(f"[bench] workload C3 1024x512 coupled, {prec}, warmup {args.warmup}, steps {args.steps}")
-    ctx = make_ctx(cmlb, [(p, fl)], prec, stream)
-    if args.tile_rows:
-        ctx.set_tile_rows(args.tile_rows)
-    ctx.set_use_graph(not args.no_graph)
+    log(f"[bench] workload {args.workload} ({len(sims)} sims, {nodes} nodes), {prec}, "
+        f"warmup {args.warmup}, steps {args.steps}")
+    ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
+                   not args.no_xcd_remap)
     gpu_s, wall_s = timed_run(ctx, args.steps, args.warmup, torch)
     inv = ctx.inventory(0)
     ctx.close()
@@ -149,40 +196,38 @@ def main():
     bpl = algorithmic_bytes_per_node(prec) * nodes
     achieved = bpl / (gpu_s / args.steps) / 1e9
     log(f"[bench] {mlups:.0f} MLUPS, {ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s "
-        f"(wall {wall_s:.3f} s)")
+        f"({achieved / HBM_PEAK_GBS:.3f} of peak; wall {wall_s:.3f} s)")
 
-    forms = {}
+    forms = {f"{args.workload}_{prec}": {"MLUPS": round(mlups, 1),
+                                         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}}
     if not args.no_forms:
-        for fp in ("fp64", "fp32", "fp16"):
-            if fp == prec:
-                forms[fp] = {"MLUPS": round(mlups, 1)}
-                continue
-            c2 = make_ctx(cmlb, [(p, fl)], fp, stream)
-            k = max(200, args.steps // 4)
-            s, _ = timed_run(c2, k, 50, torch)
-            c2.close()
-            forms[fp] = {"MLUPS": round(nodes * k / s / 1e6, 1)}
-            log(f"[bench] form {fp}: {forms[fp]['MLUPS']} MLUPS")
-        sims = W.batched_shear_drops(64)
-        bnodes = sum(s[0]["nx"] * s[0]["ny"] for s in sims)
-        for fp in ("fp32", "fp16"):
-            c3 = make_ctx(cmlb, sims, fp, stream)
-            k = 100
-            s, _ = timed_run(c3, k, 10, torch)
-            c3.close()
-            forms[f"batched64_{fp}"] = {
-                "MLUPS": round(bnodes * k / s / 1e6, 1), "nodes": bnodes,
-                "hbm_frac": round(algorithmic_bytes_per_node(fp) * bnodes / (s / k) / 1e9
-                                  / HBM_PEAK_GBS, 3)}
-            log(f"[bench] batched64 {fp}: {forms[f'batched64_{fp}']}")
-        base = forms["fp64"]["MLUPS"]
-        for v in forms.values():
-            v["speedup_vs_fp64_gpu"] = round(v["MLUPS"] / base, 2)
+        for wl in ("batched", "c3"):
+            wsims, _ = workload(W, wl) if wl != args.workload else (sims, None)
+            wnodes = sum(p["nx"] * p["ny"] for p, _ in wsims)
+            for fp in ("fp64", "fp32", "fp16"):
+                key = f"{wl}_{fp}"
+                if key in forms:
+                    continue
+                c2 = make_ctx(cmlb, wsims, fp, stream)
+                k = 200 if wl == "batched" else 2000
+                s, _ = timed_run(c2, k, 20, torch)
+                c2.close()
+                bw = algorithmic_bytes_per_node(fp) * wnodes / (s / k) / 1e9
+                forms[key] = {"MLUPS": round(wnodes * k / s / 1e6, 1),
+                              "hbm_frac": round(bw / HBM_PEAK_GBS, 4)}
+                log(f"[bench] form {key}: {forms[key]}")
+        for wl in ("batched", "c3"):
+            base = forms.get(f"{wl}_fp64", {}).get("MLUPS")
+            for fp in ("fp64", "fp32", "fp16"):
+                key = f"{wl}_{fp}"
+                if base and key in forms:
+                    forms[key]["speedup_vs_fp64_gpu"] = round(forms[key]["MLUPS"] / base, 2)
 
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] CPU oracle sample: {args.cpu_steps} steps")
-        cpu = cpu_baseline(p, fl, args.cpu_steps)
+        log("[bench] CPU oracle sample")
+        cpu = cpu_baseline(sims)
+        log(f"[bench] CPU oracle: {cpu}")
 
     out = {
         "metric": METRIC,
@@ -198,10 +243,10 @@ def main():
         "dtype": ARITH[prec],
         "data": "synthetic",
         "config": {
-            "workload": "coupled surfactant-laden shear drop, 1024x512, R=64, Ca=0.3, E=0.2, "
-                        "c0/c_max=0.3, Re=0.1, walls at +-U0",
-            "nx": p["nx"], "ny": p["ny"], "nodes": nodes, "storage": prec,
-            "lattices": 3, "graph": not args.no_graph,
+            "workload": desc,
+            "sims": len(sims), "nodes": nodes, "storage": prec, "lattices": 3,
+            "graph": not args.no_graph, "tile_rows": args.tile_rows or "default",
+            "xcd_remap": not args.no_xcd_remap,
         },
         "roofline": {
             "bound": "hbm",
@@ -209,11 +254,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_entry("c3", prec),
+            "traffic": traffic_entry(args.workload, prec),
         },
         "cpu_baseline": cpu,
         "forms": forms,
-        "inventory": {"phi": inv[0], "c": inv[1]},
+        "inventory_sim0": {"phi": inv[0], "c": inv[1]},
     }
     print(json.dumps(out), flush=True)
 

@@ -171,6 +171,11 @@ int cmlb_launch_options(const cmlb_ctx* ctx, int32_t* rows, int32_t cap);
  * Default 1.  Results do not depend on it. */
 int cmlb_set_use_graph(cmlb_ctx* ctx, int32_t on);
 
+/* Map workgroups to tiles so that each of the GPU's 8 XCDs (separate L2
+ * caches) works on a contiguous band of tiles (1, default) or in plain
+ * dispatch order (0).  Results do not depend on it. */
+int cmlb_set_xcd_remap(cmlb_ctx* ctx, int32_t on);
+
 int64_t cmlb_step_count(const cmlb_ctx* ctx);
 int32_t cmlb_num_sims(const cmlb_ctx* ctx);
 /* Message of the last error on this context (owned by the context). */

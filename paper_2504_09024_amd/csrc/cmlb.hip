@@ -28,6 +28,45 @@ bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
 
 double pow2_floor(double v) { return std::ldexp(1.0, (int)std::floor(std::log2(v))); }
 
+// Constants of one simulation in the compute type T.
+template <class T>
+void fill_consts(PhysConsts<T>& k, const SimDev& d) {
+    k.inv_f = T(1.0 / d.scale_f);
+    k.qref_f = T(d.qref_f);
+    k.inv_h = T(1.0 / d.scale_h);
+    k.inv_g = T(1.0 / d.scale_g);
+    k.scale_f = T(d.scale_f);
+    k.scale_h = T(d.scale_h);
+    k.scale_g = T(d.scale_g);
+    k.phi_a = T(d.phi_a);
+    k.phi_b = T(d.phi_b);
+    k.inv_dphi = T(d.inv_dphi);
+    k.phim = T(d.phim);
+    k.theta_k = T(d.theta_k);
+    k.thetac_k = T(d.thetac_k);
+    k.M_phi = T(d.M_phi);
+    k.D_s = T(d.D_s);
+    k.omega_k = T(d.omega_k);
+    k.omega_c = T(d.omega_c);
+    k.rho_b = T(d.rho_b);
+    k.drho = T(d.drho);
+    k.nu_b = T(d.nu_b);
+    k.dnu = T(d.dnu);
+    k.inv_rho_b = T(1.0 / d.rho_b);
+    k.omega_nu_b = T(1.0 / (3.0 * d.nu_b + 0.5));
+    k.omega_zeta = T(d.omega_zeta);
+    k.sigma0 = T(d.sigma0);
+    k.beta = T(d.beta);
+    k.c_max = T(d.c_max);
+    k.inv_cmax = T(d.c_max != 0.0 ? 1.0 / d.c_max : 0.0);
+    k.ks = T(d.ks);
+    k.u_wall = T(d.u_wall);
+    k.Fx = T(d.F_ext_x);
+    k.Fy = T(d.F_ext_y);
+    k.P_ref = T(d.P_ref);
+    k.dr_cs2 = T(d.drho * d.inv_dphi / 3.0);
+}
+
 }  // namespace
 
 struct cmlb_ctx {
@@ -51,6 +90,8 @@ struct cmlb_ctx {
     SimDev* d_sims = nullptr;
     int4* d_tiles = nullptr;
     int ntiles = 0;
+    int4* d_ftiles = nullptr;        // field-evaluation tiles (64 x 8)
+    std::vector<int> ftile0, fntiles;
     int64_t* d_step = nullptr;  // [2]
     int32_t* d_fault = nullptr; // [n_sims]
     double* d_stage = nullptr;  // staging: max(27, 5) * max_plane doubles
@@ -60,6 +101,7 @@ struct cmlb_ctx {
     int64_t step = 0;
     int tile_rows = 0;          // 0 = default
     int use_graph = 1;
+    int xcd_remap = 1;
     bool fault_seen = false;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -87,12 +129,30 @@ int fail(cmlb_ctx* c, int code, const char* fmt, ...) {
             return fail((ctx), CMLB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Launch shapes of the step kernel: tile = 64 x rows, rows = waves * rows per
+// thread.  FP64 keeps 4-wave workgroups (its registers allow two waves per
+// SIMD); the FP32-arithmetic forms also offer 8- and 16-wave workgroups at two
+// rows per thread (four waves per SIMD), whose taller tiles share more halo.
+struct Shape {
+    int rows, nw, npt;
+};
+const Shape SHAPES_64[] = {{4, 4, 1}, {8, 4, 2}};
+const Shape SHAPES_32[] = {{4, 4, 1}, {8, 4, 2}, {16, 8, 2}, {32, 16, 2}};
+
 int default_rows(int prec) { return prec == CMLB_FP64 ? 8 : 16; }
 
-bool rows_ok(int prec, int rows) {
-    if (prec == CMLB_FP64) return rows == 4 || rows == 8;
-    return rows == 4 || rows == 8 || rows == 16;
+bool shape_of(int prec, int rows, Shape* out) {
+    const Shape* t = prec == CMLB_FP64 ? SHAPES_64 : SHAPES_32;
+    const int n = prec == CMLB_FP64 ? 2 : 4;
+    for (int i = 0; i < n; ++i)
+        if (t[i].rows == rows) {
+            if (out) *out = t[i];
+            return true;
+        }
+    return false;
 }
+
+bool rows_ok(int prec, int rows) { return shape_of(prec, rows, nullptr); }
 
 // ------------------------------------------------------------------------
 // kernel selection
@@ -100,34 +160,39 @@ bool rows_ok(int prec, int rows) {
 using StepFn = void (*)(StepArgs);
 
 template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
-StepFn pick_npt(int npt) {
-    switch (npt) {
-        case 1: return k_step<S, T, FLOW, WALLS, 1, FIELDS>;
-        case 2: return k_step<S, T, FLOW, WALLS, 2, FIELDS>;
-        default: return k_step<S, T, FLOW, WALLS, 4, FIELDS>;
+StepFn pick_shape(const Shape& sh) {
+    if constexpr (FIELDS) {
+        return k_step<S, T, FLOW, WALLS, 4, 2, true>;
+    } else {
+        if (sh.nw == 4 && sh.npt == 1) return k_step<S, T, FLOW, WALLS, 4, 1, false>;
+        if (sh.nw == 4 && sh.npt == 2) return k_step<S, T, FLOW, WALLS, 4, 2, false>;
+        if constexpr (sizeof(T) == 4) {
+            if (sh.nw == 8) return k_step<S, T, FLOW, WALLS, 8, 2, false>;
+            return k_step<S, T, FLOW, WALLS, 16, 2, false>;
+        }
+        return k_step<S, T, FLOW, WALLS, 4, 2, false>;
     }
 }
 template <class S, class T, bool FIELDS>
-StepFn pick_flow(int flow, int walls, int npt) {
+StepFn pick_flow(int flow, int walls, const Shape& sh) {
     if (flow == FLOW_NONE)
-        return walls ? pick_npt<S, T, FLOW_NONE, true, FIELDS>(npt)
-                     : pick_npt<S, T, FLOW_NONE, false, FIELDS>(npt);
+        return walls ? pick_shape<S, T, FLOW_NONE, true, FIELDS>(sh)
+                     : pick_shape<S, T, FLOW_NONE, false, FIELDS>(sh);
     if (flow == FLOW_PRESCRIBED)
-        return walls ? pick_npt<S, T, FLOW_PRESCRIBED, true, FIELDS>(npt)
-                     : pick_npt<S, T, FLOW_PRESCRIBED, false, FIELDS>(npt);
-    return walls ? pick_npt<S, T, FLOW_COUPLED, true, FIELDS>(npt)
-                 : pick_npt<S, T, FLOW_COUPLED, false, FIELDS>(npt);
+        return walls ? pick_shape<S, T, FLOW_PRESCRIBED, true, FIELDS>(sh)
+                     : pick_shape<S, T, FLOW_PRESCRIBED, false, FIELDS>(sh);
+    return walls ? pick_shape<S, T, FLOW_COUPLED, true, FIELDS>(sh)
+                 : pick_shape<S, T, FLOW_COUPLED, false, FIELDS>(sh);
 }
-StepFn pick_step(int prec, int flow, int walls, int rows, bool fields) {
-    const int npt = rows / 4;
+StepFn pick_step(int prec, int flow, int walls, const Shape& sh, bool fields) {
     if (prec == CMLB_FP64)
-        return fields ? pick_flow<double, double, true>(flow, walls, npt)
-                      : pick_flow<double, double, false>(flow, walls, npt);
+        return fields ? pick_flow<double, double, true>(flow, walls, sh)
+                      : pick_flow<double, double, false>(flow, walls, sh);
     if (prec == CMLB_FP32)
-        return fields ? pick_flow<float, float, true>(flow, walls, npt)
-                      : pick_flow<float, float, false>(flow, walls, npt);
-    return fields ? pick_flow<_Float16, float, true>(flow, walls, npt)
-                  : pick_flow<_Float16, float, false>(flow, walls, npt);
+        return fields ? pick_flow<float, float, true>(flow, walls, sh)
+                      : pick_flow<float, float, false>(flow, walls, sh);
+    return fields ? pick_flow<_Float16, float, true>(flow, walls, sh)
+                  : pick_flow<_Float16, float, false>(flow, walls, sh);
 }
 
 int rows_of(const cmlb_ctx* c) { return c->tile_rows ? c->tile_rows : default_rows(c->prec); }
@@ -141,15 +206,25 @@ void drop_graphs(cmlb_ctx* c) {
     }
 }
 
-int build_tiles(cmlb_ctx* c) {
-    const int rows = rows_of(c);
+std::vector<int4> make_tiles(const cmlb_ctx* c, int rows, std::vector<int>* first,
+                            std::vector<int>* count) {
     std::vector<int4> tiles;
     for (int s = 0; s < c->n_sims; ++s) {
-        SimDev& d = c->sims[s];
-        d.tile0 = (int)tiles.size();
+        const SimDev& d = c->sims[s];
+        if (first) first->push_back((int)tiles.size());
         for (int y0 = 0; y0 < d.ny; y0 += rows)
             for (int x0 = 0; x0 < d.nx; x0 += TX) tiles.push_back(make_int4(s, x0, y0, 0));
-        d.ntiles = (int)tiles.size() - d.tile0;
+        if (count) count->push_back((int)tiles.size() - first->back());
+    }
+    return tiles;
+}
+
+int build_tiles(cmlb_ctx* c) {
+    std::vector<int> first, count;
+    std::vector<int4> tiles = make_tiles(c, rows_of(c), &first, &count);
+    for (int s = 0; s < c->n_sims; ++s) {
+        c->sims[s].tile0 = first[s];
+        c->sims[s].ntiles = count[s];
     }
     if (c->d_tiles) (void)hipFree(c->d_tiles);
     c->d_tiles = nullptr;
@@ -163,6 +238,23 @@ int build_tiles(cmlb_ctx* c) {
     return CMLB_OK;
 }
 
+// Tiles of the field-evaluation kernel (fixed 64 x 8 shape).
+int build_field_tiles(cmlb_ctx* c) {
+    c->ftile0.clear();
+    c->fntiles.clear();
+    std::vector<int4> tiles = make_tiles(c, 8, &c->ftile0, &c->fntiles);
+    HIP_TRY(c, hipMalloc(&c->d_ftiles, sizeof(int4) * tiles.size()));
+    HIP_TRY(c, hipMemcpy(c->d_ftiles, tiles.data(), sizeof(int4) * tiles.size(),
+                         hipMemcpyHostToDevice));
+    return CMLB_OK;
+}
+
+Shape shape_cur(const cmlb_ctx* c) {
+    Shape sh{8, 4, 2};
+    shape_of(c->prec, rows_of(c), &sh);
+    return sh;
+}
+
 StepArgs step_args(cmlb_ctx* c, int parity) {
     StepArgs a;
     memset(&a, 0, sizeof(a));
@@ -171,6 +263,8 @@ StepArgs step_args(cmlb_ctx* c, int parity) {
     a.sims = c->d_sims;
     a.tiles = c->d_tiles;
     a.tile_base = 0;
+    a.ntiles = c->ntiles;
+    a.xcd_remap = c->xcd_remap;
     a.ushape = c->ushape;
     a.step_in = c->d_step + parity;
     a.step_out = c->d_step + (parity ^ 1);
@@ -179,17 +273,22 @@ StepArgs step_args(cmlb_ctx* c, int parity) {
     return a;
 }
 
+// grid of the step kernel: padded to a multiple of 8 when remapping per XCD
+int step_grid(const cmlb_ctx* c) { return c->xcd_remap ? (c->ntiles + 7) / 8 * 8 : c->ntiles; }
+
 int launch_step(cmlb_ctx* c, int parity) {
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, rows_of(c), false);
+    const Shape sh = shape_cur(c);
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, sh, false);
     StepArgs a = step_args(c, parity);
-    hipLaunchKernelGGL(fn, dim3(c->ntiles), dim3(WG), 0, c->stream, a);
+    hipLaunchKernelGGL(fn, dim3(step_grid(c)), dim3(sh.nw * 64), 0, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     return CMLB_OK;
 }
 
 // Graph of 2*GRAPH_PAIRS steps starting from parity p (ends at parity p).
 int build_graph(cmlb_ctx* c, int p) {
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, rows_of(c), false);
+    const Shape sh = shape_cur(c);
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, sh, false);
     HIP_TRY(c, hipGraphCreate(&c->graph[p], 0));
     hipGraphNode_t prev = nullptr;
     for (int k = 0; k < 2 * GRAPH_PAIRS; ++k) {
@@ -198,8 +297,8 @@ int build_graph(cmlb_ctx* c, int p) {
         hipKernelNodeParams np;
         memset(&np, 0, sizeof(np));
         np.func = reinterpret_cast<void*>(fn);
-        np.gridDim = dim3(c->ntiles);
-        np.blockDim = dim3(WG);
+        np.gridDim = dim3(step_grid(c));
+        np.blockDim = dim3(sh.nw * 64);
         np.sharedMemBytes = 0;
         np.kernelParams = kargs;
         np.extra = nullptr;
@@ -233,7 +332,7 @@ void launch_decode(cmlb_ctx* c, int sim) {
     const char* base = static_cast<const char*>(c->pop[c->cur]) + d.off * (int64_t)sizeof(S);
     hipLaunchKernelGGL(k_decode<S>, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0,
                        c->stream, (const void*)base, (const SimDev*)(c->d_sims + sim), c->nlat,
-                       c->d_stage);
+                       c->walls, c->d_stage);
 }
 template <class S>
 void launch_encode(cmlb_ctx* c, int sim) {
@@ -242,7 +341,7 @@ void launch_encode(cmlb_ctx* c, int sim) {
     char* base = static_cast<char*>(c->pop[c->cur]) + d.off * (int64_t)sizeof(S);
     hipLaunchKernelGGL(k_encode<S>, dim3((unsigned)((total + WG - 1) / WG)), dim3(WG), 0,
                        c->stream, (void*)base, (const SimDev*)(c->d_sims + sim), c->nlat,
-                       (const double*)c->d_stage);
+                       c->walls, (const double*)c->d_stage);
 }
 template <class S>
 void launch_inventory(cmlb_ctx* c, int sim) {
@@ -267,6 +366,7 @@ void release(cmlb_ctx* c) {
     (void)hipFree(c->ushape);
     (void)hipFree(c->d_sims);
     (void)hipFree(c->d_tiles);
+    (void)hipFree(c->d_ftiles);
     (void)hipFree(c->d_step);
     (void)hipFree(c->d_fault);
     (void)hipFree(c->d_stage);
@@ -293,7 +393,7 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
     if (bc != CMLB_BC_PERIODIC && bc != CMLB_BC_MOVING_WALLS) return CMLB_EINVAL;
     const int nlat = flow == CMLB_FLOW_COUPLED ? 3 : 2;
     std::vector<SimDev> sims(n_sims);
-    int64_t off = 0, uoff = 0, max_plane = 0;
+    int64_t off = 0, uoff = 0, max_plane = 0, node_count = 0;
     int max_ny = 0;
     for (int s = 0; s < n_sims; ++s) {
         const cmlb_sim_params& p = params[s];
@@ -357,7 +457,15 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
             d.qref_f = 0.0;
             d.scale_f = d.scale_h = d.scale_g = 1.0;
         }
+        if ((int64_t)9 * plane * (int64_t)storage_bytes(precision) > (int64_t)INT32_MAX)
+            return CMLB_EINVAL;  // a lattice must fit a 32-bit buffer range
+        d.node_base = (uint32_t)node_count;
+        d.uniform_rho = p.rho_a == p.rho_b;
+        d.uniform_nu = p.nu_a == p.nu_b;
+        fill_consts(d.kd, d);
+        fill_consts(d.kf, d);
         sims[s] = d;
+        node_count += plane;
         off += (int64_t)nlat * 9 * plane;
         if (flow == CMLB_FLOW_PRESCRIBED) uoff += 2 * plane;
         max_plane = std::max(max_plane, plane);
@@ -408,6 +516,7 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
     if (hipMemset(c->d_step, 0, sizeof(int64_t) * 2) != hipSuccess) return bail(CMLB_EDEVICE);
     if (hipMemset(c->d_fault, 0, sizeof(int32_t) * n_sims) != hipSuccess) return bail(CMLB_EDEVICE);
     if (build_tiles(c) != CMLB_OK) return bail(CMLB_EDEVICE);
+    if (build_field_tiles(c) != CMLB_OK) return bail(CMLB_EDEVICE);
     *out = c;
     return CMLB_OK;
 }
@@ -494,13 +603,17 @@ int cmlb_read_fields(cmlb_ctx* c, int32_t sim, double* phi, double* cc, double* 
     if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
     const SimDev& d = c->sims[sim];
     const int64_t plane = (int64_t)d.nx * d.ny;
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, rows_of(c), true);
+    const Shape fsh{8, 4, 2};
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, fsh, true);
     StepArgs a = step_args(c, c->cur);
     a.dst = nullptr;
     a.step_out = nullptr;
-    a.tile_base = d.tile0;
+    a.tiles = c->d_ftiles;
+    a.tile_base = c->ftile0[sim];
+    a.ntiles = c->fntiles[sim];
+    a.xcd_remap = 0;
     a.fields_out = c->d_stage;
-    hipLaunchKernelGGL(fn, dim3(d.ntiles), dim3(WG), 0, c->stream, a);
+    hipLaunchKernelGGL(fn, dim3(c->fntiles[sim]), dim3(fsh.nw * 64), 0, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double* outs[5] = {phi, cc, ux, uy, p};
@@ -607,17 +720,23 @@ int cmlb_set_tile_rows(cmlb_ctx* c, int32_t rows) {
 
 int cmlb_launch_options(const cmlb_ctx* c, int32_t* rows, int32_t cap) {
     if (!c || (!rows && cap > 0)) return CMLB_EINVAL;
-    const int opts64[] = {4, 8};
-    const int opts32[] = {4, 8, 16};
-    const int* o = c->prec == CMLB_FP64 ? opts64 : opts32;
-    const int n = c->prec == CMLB_FP64 ? 2 : 3;
-    for (int i = 0; i < n && i < cap; ++i) rows[i] = o[i];
+    const Shape* t = c->prec == CMLB_FP64 ? SHAPES_64 : SHAPES_32;
+    const int n = c->prec == CMLB_FP64 ? 2 : 4;
+    for (int i = 0; i < n && i < cap; ++i) rows[i] = t[i].rows;
     return n;
 }
 
 int cmlb_set_use_graph(cmlb_ctx* c, int32_t on) {
     if (!c) return CMLB_EINVAL;
     c->use_graph = on ? 1 : 0;
+    return CMLB_OK;
+}
+
+int cmlb_set_xcd_remap(cmlb_ctx* c, int32_t on) {
+    if (!c) return CMLB_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->xcd_remap = on ? 1 : 0;
+    drop_graphs(c);
     return CMLB_OK;
 }
 

@@ -2,27 +2,31 @@
 // gfx950.  One fused kernel performs a whole time step for every tile of
 // every simulation in the context:
 //
-//   phase 1  load the 27 (18 without flow) pre-collision populations of the
-//            tile's own nodes into registers; zeroth moments phi, c and the
-//            pressure deviation P^ - P_ref go to LDS; the halo ring
-//            (radius 2 for phi, radius 1 for c and P^) is summed from the
-//            neighbours' populations;
+//   phase 1  pull the 27 (18 without flow) pre-collision populations of the
+//            tile's own nodes into registers, q_a(x) = q~_a(x - e_a); zeroth
+//            moments phi, c and the pressure deviation P^ - P_ref go to LDS;
+//            the halo ring (radius 2 for phi, radius 1 for c and P^) is
+//            summed from pulled populations too;
 //   phase 2  unit normal n = grad phi/(|grad phi| + eps) on the radius-1
 //            ring (coupled flow only, it feeds the curvature);
 //   phase 3  per node: interface geometry (theta, theta_c, curvature),
 //            Langmuir sigma(c), F_s, F_p, u, P; central-moment collisions
-//            of f, h and g; push-streaming of the post-collision
-//            populations to the neighbours (half-way bounce-back at walls).
+//            of f, h and g; the post-collision populations are stored at the
+//            node itself (aligned stores).
 //
-// The population state between steps is the pre-collision state at each
-// node (push form), so the zeroth moments of any node are local sums.
+// Between steps the buffer holds post-collision populations at their own
+// node (pull form): reads carry the neighbour shift, writes are aligned,
+// which is the faster of the two streaming forms when the working set lives
+// in HBM.  At a moving wall (half-way bounce-back) a node pulls the
+// directions that would come from behind the wall out of its own opposite
+// slots; the momentum correction of g is added when those slots are stored.
 #pragma once
 #include "lattice.hpp"
 
 namespace cmlb {
 
 constexpr int TX = 64;          // tile width: one wavefront across x
-constexpr int WG = 256;         // threads per workgroup (4 waves)
+constexpr int WG = 256;         // threads per workgroup of the auxiliary kernels
 constexpr double NORMAL_EPS = 1e-12;
 
 struct StepArgs {
@@ -31,6 +35,8 @@ struct StepArgs {
     const SimDev* sims;
     const int4* tiles;      // (sim, x0, y0, -)
     int32_t tile_base;
+    int32_t ntiles;         // tiles of this launch
+    int32_t xcd_remap;      // grid padded to a multiple of 8, remapped per XCD
     int32_t pad_;
     const void* ushape;     // prescribed velocity shapes, compute type
     const int64_t* step_in; // step counter read by this launch
@@ -48,12 +54,72 @@ struct Store<_Float16> {
     static constexpr bool scaled = true;
 };
 
-// Load the nine stored values of a scalar lattice (q_a/w_a - qref, scaled).
-template <class S, class T>
-__device__ __forceinline__ void load9(const S* __restrict__ p, int plane, T v[9]) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) v[a] = T(p[a * plane]);
+// ---------------------------------------------------------------------------
+// Storage access through buffer descriptors: one descriptor per lattice, the
+// node offset in a VGPR and the direction plane in the SGPR offset, so the 27
+// loads and stores of a node share one address computation.  Out-of-range
+// buffer accesses return 0 / are dropped by the hardware.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
 }
+
+template <class S>
+struct Buf;
+template <>
+struct Buf<double> {
+    static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, double v,
+                                                 uint32_t) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<float> {
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
+                                                 uint32_t) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, 0);
+    }
+};
+// binary16 storage: loads widen exactly; stores round stochastically with
+// gfx950's v_cvt_sr_f16_f32 (the top 13 bits of the random word decide the
+// rounding direction; exactly representable values are kept).  Stochastic
+// rounding keeps the per-step storage errors independent and unbiased, where
+// round-to-nearest would repeat the same error every step at a quasi-steady
+// node.
+template <>
+struct Buf<_Float16> {
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+        return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)));
+    }
+    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
+                                                 uint32_t rnd) {
+        const h16x2 h = __builtin_amdgcn_cvt_sr_f16_f32(h16x2{}, v, rnd, false);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, so, 0);
+    }
+};
+
+// Counter-based random words for the stochastic rounding: the MurmurHash3
+// 32-bit finaliser of (node, step) gives a per-node seed; the word for store
+// k of the node is seed + k * 0x9E3779B9 (a Weyl sequence: one add each, and
+// its top bits -- the ones the conversion uses -- are equidistributed).
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ constexpr uint32_t weyl(int k) { return (uint32_t)k * 0x9E3779B9u; }
 
 // Moments of stored scalar-lattice values in storage units.  No FP
 // contraction: a node's zeroth moment must carry the same bits in every code
@@ -70,112 +136,179 @@ __device__ __forceinline__ T scalar_zeroth_nc(const T v[9]) {
     scalar_moments(v, m0, m1, m2);
     return m0;
 }
-
-// Decode nine stored values of g to deviations d_a = w_a s_a inv.
-template <class S, class T>
-__device__ __forceinline__ void decode_dev(const S* __restrict__ p, int plane, T inv, T d[9]) {
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const T s = T(p[a * plane]);
-        if (Store<S>::scaled)
-            d[a] = wgt<T>(a) * (s * inv);
-        else
-            d[a] = wgt<T>(a) * s;
-    }
-}
-
 template <class T>
 __device__ __forceinline__ T zeroth(const T d[9]) {
 #pragma clang fp contract(off)
     return sum9(d);
 }
-
 template <class T>
 __device__ __forceinline__ Raw6<T> moments6_nc(const T d[9]) {
 #pragma clang fp contract(off)
     return raw_moments6(d);
 }
 
-template <class T>
-struct Consts {
-    T inv_f, qref_f, inv_h, inv_g;
-    T scale_f, scale_h, scale_g;
-    T phi_a, phi_b, inv_dphi, phim, theta_k, thetac_k;
-    T M_phi, D_s, omega_k, omega_c;
-    T rho_b, drho, nu_b, dnu, omega_zeta;
-    T sigma0, beta, c_max, ks;
-    T u_wall, Fx, Fy, P_ref;
-};
+template <class S, class T>
+__device__ __forceinline__ void load9(__amdgpu_buffer_rsrc_t r, int vo, int pb, T v[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) v[a] = T(Buf<S>::load(r, vo, a * pb));
+}
+// g: deviations d_a = w_a s_a / scale
+template <class S, class T>
+__device__ __forceinline__ void load9_dev(__amdgpu_buffer_rsrc_t r, int vo, int pb, T inv, T d[9]) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const T s = T(Buf<S>::load(r, vo, a * pb));
+        d[a] = Store<S>::scaled ? wgt<T>(a) * (s * inv) : wgt<T>(a) * s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pulled loads.  For a node whose nine sources x - e_a all lie inside the
+// grid, the source shift goes into the scalar offset: so[a] = a*plane -
+// (e_ax + e_ay nx), in bytes (non-negative for a >= 1 because a plane holds
+// at least four rows), and the node offset is shared by all nine loads.
+// Near the domain edge the sources wrap (periodic) or, behind a wall, come
+// from the node's own opposite slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pull_offsets(int pb, int nx, int sb, int so[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) so[a] = a * pb - (EXa(a) + EYa(a) * nx) * sb;
+}
+
+template <class S, class T>
+__device__ __forceinline__ void pull9_inner(__amdgpu_buffer_rsrc_t r, int vo, const int so[9], T v[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) v[a] = T(Buf<S>::load(r, vo, so[a]));
+}
+
+template <class S, class T, bool WALLS>
+__device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int pb, int lx, int ly,
+                                           int nx, int ny, T v[9]) {
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        int sx = lx - EXa(a), sy = ly - EYa(a), pa = a;
+        if (sx < 0) sx += nx;
+        else if (sx >= nx) sx -= nx;
+        if (sy < 0 || sy >= ny) {
+            if (WALLS) {
+                pa = OPPa(a);
+                sx = lx;
+                sy = ly;
+            } else {
+                sy = sy < 0 ? sy + ny : sy - ny;
+            }
+        }
+        v[a] = T(Buf<S>::load(r, (sy * nx + sx) * (int)sizeof(S), pa * pb));
+    }
+}
+
+// stored g values -> deviations d_a = w_a s_a / scale
+template <class S, class T>
+__device__ __forceinline__ void to_dev(T v[9], T inv) {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int a = 0; a < 9; ++a) v[a] = Store<S>::scaled ? wgt<T>(a) * (v[a] * inv) : wgt<T>(a) * v[a];
+}
+
+// Slot from which node (x, y) pulls direction a: (plane, node index).
+__device__ __forceinline__ void pull_slot(int x, int y, int a, int nx, int ny, bool walls,
+                                          int& plane_a, int& node) {
+    int sx = x - EXa(a), sy = y - EYa(a);
+    plane_a = a;
+    if (sx < 0) sx += nx;
+    else if (sx >= nx) sx -= nx;
+    if (sy < 0 || sy >= ny) {
+        if (walls) {
+            plane_a = OPPa(a);
+            sx = x;
+            sy = y;
+        } else {
+            sy = sy < 0 ? sy + ny : sy - ny;
+        }
+    }
+    node = sy * nx + sx;
+}
 
 template <class T>
-__device__ __forceinline__ Consts<T> load_consts(const SimDev* sd) {
-    Consts<T> k;
-    k.scale_f = T(sd->scale_f);
-    k.scale_h = T(sd->scale_h);
-    k.scale_g = T(sd->scale_g);
-    k.inv_f = T(1.0 / sd->scale_f);
-    k.inv_h = T(1.0 / sd->scale_h);
-    k.inv_g = T(1.0 / sd->scale_g);
-    k.qref_f = T(sd->qref_f);
-    k.phi_a = T(sd->phi_a);
-    k.phi_b = T(sd->phi_b);
-    k.inv_dphi = T(sd->inv_dphi);
-    k.phim = T(sd->phim);
-    k.theta_k = T(sd->theta_k);
-    k.thetac_k = T(sd->thetac_k);
-    k.M_phi = T(sd->M_phi);
-    k.D_s = T(sd->D_s);
-    k.omega_k = T(sd->omega_k);
-    k.omega_c = T(sd->omega_c);
-    k.rho_b = T(sd->rho_b);
-    k.drho = T(sd->drho);
-    k.nu_b = T(sd->nu_b);
-    k.dnu = T(sd->dnu);
-    k.omega_zeta = T(sd->omega_zeta);
-    k.sigma0 = T(sd->sigma0);
-    k.beta = T(sd->beta);
-    k.c_max = T(sd->c_max);
-    k.ks = T(sd->ks);
-    k.u_wall = T(sd->u_wall);
-    k.Fx = T(sd->F_ext_x);
-    k.Fy = T(sd->F_ext_y);
-    k.P_ref = T(sd->P_ref);
-    return k;
+__device__ __forceinline__ const PhysConsts<T>& consts(const SimDev* sd);
+template <>
+__device__ __forceinline__ const PhysConsts<double>& consts<double>(const SimDev* sd) {
+    return sd->kd;
 }
+template <>
+__device__ __forceinline__ const PhysConsts<float>& consts<float>(const SimDev* sd) {
+    return sd->kf;
+}
+
+// Fast approximate operations for the FP32 path (1-2 ulp), exact IEEE ones
+// for FP64 (the FP64 path is checked against the oracle at 1e-12).
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float log_(float x) { return __logf(x); }
+__device__ __forceinline__ double log_(double x) { return log(x); }
 
 // ---------------------------------------------------------------------------
 // The fused step kernel.  FIELDS = true evaluates phases 1-3 up to the
 // macroscopic fields and writes them instead of colliding.
 // ---------------------------------------------------------------------------
-template <class S, class T, int FLOW, bool WALLS, int NPT, bool FIELDS>
-__global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
+// Launch shape: NW waves per workgroup, NPT rows per thread, tile 64 x NW*NPT.
+// At most 128 VGPRs for FP32 storage so that four waves fit per SIMD.
+template <class T, int NW>
+struct Occupancy {
+    static constexpr int waves_per_eu = sizeof(T) == 4 ? 4 : (NW >= 8 ? 2 : 2);
+};
+
+template <class S, class T, int FLOW, bool WALLS, int NW, int NPT, bool FIELDS>
+__global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_step(const StepArgs a) {
+    constexpr int NT = NW * 64;
     constexpr bool CPL = FLOW == FLOW_COUPLED;
     constexpr bool MOV = FLOW != FLOW_NONE;
-    constexpr int NL = CPL ? 3 : 2;
-    constexpr int TY = 4 * NPT;
+    constexpr int TY = NW * NPT;
     constexpr int PW = TX + 4, PH = TY + 4;  // phi region (radius 2)
     constexpr int QW = TX + 2, QH = TY + 2;  // c, P^, n region (radius 1)
     constexpr int RING = 4 * PW + 4 * TY;
+    constexpr int SB = sizeof(S);
     __shared__ T phiL[PH * PW];
     __shared__ T cL[QH * QW];
     __shared__ T pL[CPL ? QH * QW : 1];
     __shared__ T nxL[CPL ? QH * QW : 1];
     __shared__ T nyL[CPL ? QH * QW : 1];
 
-    const int4 tl = a.tiles[a.tile_base + blockIdx.x];
+    // Workgroups are dispatched round-robin over the 8 XCDs (each with its
+    // own L2): give XCD k the contiguous tile range [k*per, (k+1)*per) so that
+    // neighbouring tiles, whose rows and halos overlap, share one L2.
+    int tix = blockIdx.x;
+    if (a.xcd_remap) {
+        const int per = (int)gridDim.x >> 3;
+        tix = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+        if (tix >= a.ntiles) return;
+    }
+    const int4 tl = a.tiles[a.tile_base + tix];
     const SimDev* sd = a.sims + tl.x;
+    const PhysConsts<T>& k = consts<T>(sd);
     const int nx = sd->nx, ny = sd->ny;
     const int x0 = tl.y, y0 = tl.z;
     const int plane = nx * ny;
-    const S* __restrict__ src = static_cast<const S*>(a.src) + sd->off;
-    const Consts<T> k = load_consts<T>(sd);
+    const int pb = plane * SB;       // bytes per direction plane
+    const int lb = 9 * pb;           // bytes per lattice
+    const char* srcb = static_cast<const char*>(a.src) + sd->off * SB;
+    const __amdgpu_buffer_rsrc_t rF = make_rsrc(srcb, lb);
+    const __amdgpu_buffer_rsrc_t rH = make_rsrc(srcb + lb, lb);
+    const __amdgpu_buffer_rsrc_t rG = make_rsrc(srcb + (CPL ? 2 * lb : 0), lb);
     const int64_t step = *a.step_in;
+    // tile, its radius-2 halo and their pull sources inside the grid: no
+    // wrapping, no walls
+    const bool inner = x0 >= 3 && x0 + TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
+    int so[9];
+    pull_offsets(pb, nx, SB, so);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int gx = x0 + lane;
-    const int lx = wrap_coord(gx, nx);
+    const int lx = inner ? gx : wrap_coord(gx, nx);
 
     // ---------------- phase 1: own nodes -----------------------------------
     T qf[NPT][9], qh[NPT][9], qg[CPL ? NPT : 1][9];
@@ -185,10 +318,21 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
     for (int j = 0; j < NPT; ++j) {
         const int iy = wave * NPT + j;
         const int gy = y0 + iy;
-        const int ly = WALLS ? mirror_coord(gy, ny) : wrap_coord(gy, ny);
-        const int nidx = ly * nx + lx;
-        load9<S, T>(src + nidx, plane, qf[j]);
-        load9<S, T>(src + 9 * plane + nidx, plane, qh[j]);
+        if (inner) {
+            const int vo = (gy * nx + gx) * SB;
+            pull9_inner<S, T>(rF, vo, so, qf[j]);
+            pull9_inner<S, T>(rH, vo, so, qh[j]);
+            if constexpr (CPL) pull9_inner<S, T>(rG, vo, so, qg[j]);
+        } else {
+            const int ly = WALLS ? mirror_coord(gy, ny) : wrap_coord(gy, ny);
+            pull9_edge<S, T, WALLS>(rF, pb, lx, ly, nx, ny, qf[j]);
+            pull9_edge<S, T, WALLS>(rH, pb, lx, ly, nx, ny, qh[j]);
+            if constexpr (CPL) pull9_edge<S, T, WALLS>(rG, pb, lx, ly, nx, ny, qg[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const int iy = wave * NPT + j;
         scalar_moments_nc(qf[j], phn[j], jfx[j], jfy[j]);
         scalar_moments_nc(qh[j], chn[j], jhx[j], jhy[j]);
         // true zeroth and first moments
@@ -201,13 +345,13 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
         phiL[(iy + 2) * PW + lane + 2] = phv[j];
         cL[(iy + 1) * QW + lane + 1] = cv[j];
         if constexpr (CPL) {
-            decode_dev<S, T>(src + 18 * plane + nidx, plane, k.inv_g, qg[j]);
+            to_dev<S, T>(qg[j], k.inv_g);
             mg[j] = moments6_nc(qg[j]);
             pL[(iy + 1) * QW + lane + 1] = mg[j].m0;
         }
     }
     // ---------------- phase 1b: halo ring ----------------------------------
-    for (int i = tid; i < RING; i += WG) {
+    for (int i = tid; i < RING; i += NT) {
         int ry, rx;
         if (i < 2 * PW) {
             ry = i / PW;
@@ -224,19 +368,36 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
             ry = 2 + (j >> 1);
             rx = (j & 1) + side * (PW - 2);
         }
-        const int hx = wrap_coord(x0 - 2 + rx, nx);
-        const int hy = WALLS ? mirror_coord(y0 - 2 + ry, ny) : wrap_coord(y0 - 2 + ry, ny);
-        const int nidx = hy * nx + hx;
+        int hx = x0 - 2 + rx, hy = y0 - 2 + ry;
+        const bool r1 = ry >= 1 && ry <= PH - 2 && rx >= 1 && rx <= PW - 2;
+        const int qi = (ry - 1) * QW + rx - 1;
         T q[9];
-        load9<S, T>(src + nidx, plane, q);
-        phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
-        if (ry >= 1 && ry <= PH - 2 && rx >= 1 && rx <= PW - 2) {
-            const int qi = (ry - 1) * QW + rx - 1;
-            load9<S, T>(src + 9 * plane + nidx, plane, q);
-            cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
-            if constexpr (CPL) {
-                decode_dev<S, T>(src + 18 * plane + nidx, plane, k.inv_g, q);
-                pL[qi] = zeroth(q);
+        if (inner) {
+            const int vo = (hy * nx + hx) * SB;
+            pull9_inner<S, T>(rF, vo, so, q);
+            phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
+            if (r1) {
+                pull9_inner<S, T>(rH, vo, so, q);
+                cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
+                if constexpr (CPL) {
+                    pull9_inner<S, T>(rG, vo, so, q);
+                    to_dev<S, T>(q, k.inv_g);
+                    pL[qi] = zeroth(q);
+                }
+            }
+        } else {
+            hx = wrap_coord(hx, nx);
+            hy = WALLS ? mirror_coord(hy, ny) : wrap_coord(hy, ny);
+            pull9_edge<S, T, WALLS>(rF, pb, hx, hy, nx, ny, q);
+            phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
+            if (r1) {
+                pull9_edge<S, T, WALLS>(rH, pb, hx, hy, nx, ny, q);
+                cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
+                if constexpr (CPL) {
+                    pull9_edge<S, T, WALLS>(rG, pb, hx, hy, nx, ny, q);
+                    to_dev<S, T>(q, k.inv_g);
+                    pL[qi] = zeroth(q);
+                }
             }
         }
     }
@@ -244,11 +405,11 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
 
     // ---------------- phase 2: unit normal on the radius-1 region ----------
     if constexpr (CPL) {
-        for (int i = tid; i < QH * QW; i += WG) {
+        for (int i = tid; i < QH * QW; i += NT) {
             const int qy = i / QW, qx = i - qy * QW;
             T gxv, gyv;
             lds_grad<T, PW>(phiL, (qy + 1) * PW + qx + 1, gxv, gyv);
-            const T inv = T(1) / (sqrt(gxv * gxv + gyv * gyv) + T(NORMAL_EPS));
+            const T inv = rcp_(sqrt_(gxv * gxv + gyv * gyv) + T(NORMAL_EPS));
             nxL[i] = gxv * inv;
             nyL[i] = gyv * inv;
         }
@@ -260,13 +421,18 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
     if constexpr (FLOW == FLOW_PRESCRIBED) {
         if (sd->vel_period_T != 0.0) tf = T(cos(M_PI * (double)step / sd->vel_period_T));
     }
-    S* __restrict__ dst = static_cast<S*>(a.dst) + sd->off;
+    char* dstb = static_cast<char*>(a.dst) + sd->off * SB;
+    const __amdgpu_buffer_rsrc_t wF = make_rsrc(dstb, lb);
+    const __amdgpu_buffer_rsrc_t wH = make_rsrc(dstb + lb, lb);
+    const __amdgpu_buffer_rsrc_t wG = make_rsrc(dstb + (CPL ? 2 * lb : 0), lb);
+    const bool urho = sd->uniform_rho, unu = sd->uniform_nu;
+    const uint32_t step_key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
     int fault = 0;
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
         const int iy = wave * NPT + j;
         const int gy = y0 + iy;
-        const bool valid = gx < nx && gy < ny;
+        const bool valid = inner || (gx < nx && gy < ny);
         const int pidx = (iy + 2) * PW + lane + 2;
         const int qidx = (iy + 1) * QW + lane + 1;
         const T phi = phv[j], c = cv[j];
@@ -278,7 +444,7 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
             nxv = nxL[qidx];
             nyv = nyL[qidx];
         } else {
-            const T inv = T(1) / (sqrt(gm2) + T(NORMAL_EPS));
+            const T inv = rcp_(sqrt_(gm2) + T(NORMAL_EPS));
             nxv = gpx * inv;
             nyv = gpy * inv;
         }
@@ -295,13 +461,13 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
             lds_grad<T, QW>(pL, qidx, gqx, gqy);
             const T curv = dnx_dx + dny_dy;
             const T lam = (phi - k.phi_b) * k.inv_dphi;
-            rho = k.rho_b + lam * k.drho;
-            const T nu = k.nu_b + lam * k.dnu;
-            omega_nu = T(1) / (T(3) * nu + T(0.5));
-            const T arg = T(1) - c / k.c_max;
-            const T sigma = k.sigma0 * (T(1) + k.beta * log(arg));
+            rho = urho ? k.rho_b : k.rho_b + lam * k.drho;
+            const T inv_rho = urho ? k.inv_rho_b : rcp_(rho);
+            omega_nu = unu ? k.omega_nu_b : rcp_(T(3) * (k.nu_b + lam * k.dnu) + T(0.5));
+            const T arg = T(1) - c * k.inv_cmax;
+            const T sigma = k.sigma0 * (T(1) + k.beta * log_(arg));
             if (valid && (!(arg > T(0)) || !(sigma >= T(0)))) fault |= 2;
-            const T dsig = -k.sigma0 * k.beta / (k.c_max - c);
+            const T dsig = -k.sigma0 * k.beta * rcp_(k.c_max - c);
             const T gsx = dsig * gcx, gsy = dsig * gcy;
             const T nd = nxv * gsx + nyv * gsy;
             const T tsx = gsx - nxv * nd, tsy = gsy - nyv * nd;
@@ -309,10 +475,8 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
             ftx = wk * (tsx - sigma * curv * nxv) + k.Fx;
             fty = wk * (tsy - sigma * curv * nyv) + k.Fy;
             // F_p = -grad psi^, psi^ = P^ - rho cs2, rho linear in phi
-            const T dr = k.drho * k.inv_dphi * K<T>::cs2;
-            fpx = -(gqx - dr * gpx);
-            fpy = -(gqy - dr * gpy);
-            const T inv_rho = T(1) / rho;
+            fpx = -(gqx - k.dr_cs2 * gpx);
+            fpy = -(gqy - k.dr_cs2 * gpy);
             ux = (T(3) * mg[j].m1 + T(0.5) * ftx) * inv_rho;
             uy = (T(3) * mg[j].m2 + T(0.5) * fty) * inv_rho;
             gam = fpx * ux + fpy * uy;
@@ -324,9 +488,7 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
             ux = us[ni] * tf;
             uy = us[plane + ni] * tf;
         }
-        if (valid && !(isfinite(phi) && isfinite(c) && isfinite(ux) && isfinite(uy) &&
-                       isfinite(dP)))
-            fault |= 1;
+        if (valid && !isfinite(phi + c + ux + uy + dP)) fault |= 1;
 
         if constexpr (FIELDS) {
             if (valid) {
@@ -367,42 +529,39 @@ __global__ __launch_bounds__(WG) void k_step(const StepArgs a) {
                 flow_collide(mg[j], ux, uy, dP, psi, P_hat, fpx, fpy, ftx, fty, gam,
                              k.omega_zeta, omega_nu, t);
                 flow_post_raw(t, ux, uy, k.P_ref, r);
-                pinv_encode(r, k.scale_g, T(0), s);
+                pinv_dev(r, k.scale_g, s);
 #pragma unroll
                 for (int q = 0; q < 9; ++q) qg[j][q] = s[q];
             }
             if (valid) {
-                const T corr = T(2) * rho * k.u_wall * k.scale_g;  // 2 rho |u_w| scale
+                const int own = gy * nx + gx;
+                const int vo = own * SB;
+                uint32_t rs = 0;
+                if constexpr (Store<S>::scaled) rs = fmix32(sd->node_base + (uint32_t)own) ^ step_key;
+                // moving wall: the slots of directions pointing into the wall
+                // are pulled back by this node next step (half-way
+                // bounce-back); g carries the momentum correction
+                // 2 rho (e_opp . u_w) in storage units, u_w = -+u_wall.
+                T wcorr = T(0);
+                int wdir = 0;
+                if (WALLS) {
+                    if (gy == 0) { wdir = -1; wcorr = T(2) * rho * k.u_wall * k.scale_g; }
+                    if (gy == ny - 1) { wdir = 1; wcorr = -T(2) * rho * k.u_wall * k.scale_g; }
+                }
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    const int ex = EXa(q), ey = EYa(q);
-                    int dx = gx + ex, dy = gy + ey;
-                    int dq = q;
-                    T cg = T(0);
-                    if (WALLS && (dy < 0 || dy >= ny)) {
-                        dq = OPPa(q);
-                        dx = gx;
-                        // e_opp . u_w with u_w = -u_wall below, +u_wall above
-                        const int exo = EXa(dq);
-                        cg = (dy < 0 ? -corr : corr) * T(exo);
-                        dy = gy;
-                    } else {
-                        if (dx >= nx) dx -= nx;
-                        if (dx < 0) dx += nx;
-                        if (!WALLS) {
-                            if (dy >= ny) dy -= ny;
-                            if (dy < 0) dy += ny;
-                        }
+                    const int so_q = q * pb;
+                    Buf<S>::store(wF, vo, so_q, qf[j][q], rs + weyl(3 * q));
+                    Buf<S>::store(wH, vo, so_q, qh[j][q], rs + weyl(3 * q + 1));
+                    if constexpr (CPL) {
+                        T v = qg[j][q];
+                        if (WALLS && wdir != 0 && EYa(q) == wdir) v += wcorr * T(EXa(q));
+                        Buf<S>::store(wG, vo, so_q, v, rs + weyl(3 * q + 2));
                     }
-                    const int o = dq * plane + dy * nx + dx;
-                    dst[o] = S(qf[j][q]);
-                    dst[9 * plane + o] = S(qh[j][q]);
-                    if constexpr (CPL) dst[18 * plane + o] = S(qg[j][q] + cg);
                 }
             }
         }
     }
-    (void)NL;
     if (fault) atomicOr(a.fault + tl.x, fault);
     if constexpr (!FIELDS) {
         if (blockIdx.x == 0 && tid == 0) *a.step_out = step + 1;
@@ -425,6 +584,9 @@ struct InitArgs {
     int32_t flow, walls;
 };
 
+// Each node computes its pre-collision equilibria and writes each direction
+// into the slot it will pull that direction from, so the first step sees
+// exactly these populations (every slot has one writer).
 template <class S, class T>
 __global__ __launch_bounds__(WG) void k_init(const InitArgs a) {
     const SimDev* sd = a.sd;
@@ -452,16 +614,15 @@ __global__ __launch_bounds__(WG) void k_init(const InitArgs a) {
     const double theta = sd->theta_k * (sd->phi_a - phi) * (phi - sd->phi_b) * sd->inv_dphi;
     const double theta_c = sd->thetac_k * c * (sd->phim - phi) * sd->inv_dphi;
     S* pop = static_cast<S*>(a.pop);
-    double r[9], s[9];
+    double r[9], sf[9], sh[9], sg[9];
     scalar_post_dev<double, true>(phi, sd->M_phi * theta * nxv, sd->M_phi * theta * nyv, ux, uy, r);
-    pinv_dev(r, sd->scale_f, s);
+    pinv_dev(r, sd->scale_f, sf);
     const double phin = (phi - sd->qref_f) * sd->scale_f;
-    for (int q = 0; q < 9; ++q) pop[q * plane + i] = S(phin + s[q]);
     scalar_post_dev<double, true>(c, sd->D_s * theta_c * nxv, sd->D_s * theta_c * nyv, ux, uy, r);
-    pinv_dev(r, sd->scale_h, s);
+    pinv_dev(r, sd->scale_h, sh);
     const double chn = c * sd->scale_h;
-    for (int q = 0; q < 9; ++q) pop[(9 + q) * plane + i] = S(chn + s[q]);
-    if (a.flow == FLOW_COUPLED) {
+    const bool cpl = a.flow == FLOW_COUPLED;
+    if (cpl) {
         const double lam = (phi - sd->phi_b) * sd->inv_dphi;
         const double rho = sd->rho_b + lam * sd->drho;
         const double P = a.P ? a.P[i] : rho * K<double>::cs2;
@@ -469,8 +630,14 @@ __global__ __launch_bounds__(WG) void k_init(const InitArgs a) {
         double t[9];
         flow_eq_dev(P - sd->P_ref, psi, ux, uy, t);
         flow_post_raw(t, ux, uy, sd->P_ref, r);
-        pinv_encode(r, sd->scale_g, 0.0, s);
-        for (int q = 0; q < 9; ++q) pop[(18 + q) * plane + i] = S(s[q]);
+        pinv_encode(r, sd->scale_g, 0.0, sg);
+    }
+    for (int q = 0; q < 9; ++q) {
+        int pq, node;
+        pull_slot(x, y, q, nx, ny, a.walls != 0, pq, node);
+        pop[pq * plane + node] = S(phin + sf[q]);
+        pop[(9 + pq) * plane + node] = S(chn + sh[q]);
+        if (cpl) pop[(18 + pq) * plane + node] = S(sg[q]);
     }
     if (a.flow == FLOW_PRESCRIBED && a.ushape) {
         T* us = static_cast<T*>(a.ushape);
@@ -480,18 +647,22 @@ __global__ __launch_bounds__(WG) void k_init(const InitArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Population transfer: decode to / encode from plain FP64 populations.
+// Population transfer: the pre-collision populations of each node (pulled
+// from their slots) to plain FP64, and back.
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(WG) void k_decode(const void* pop, const SimDev* sd, int nlat,
-                                               double* out) {
-    const int plane = sd->nx * sd->ny;
+                                               int walls, double* out) {
+    const int nx = sd->nx, ny = sd->ny, plane = nx * ny;
     const int64_t total = (int64_t)nlat * 9 * plane;
     const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= total) return;
     const int lat = (int)(i / (9 * (int64_t)plane));
     const int q = (int)((i / plane) % 9);
-    const double s = double(static_cast<const S*>(pop)[i]);
+    const int n = (int)(i % plane);
+    int pq, node;
+    pull_slot(n % nx, n / nx, q, nx, ny, walls != 0, pq, node);
+    const double s = double(static_cast<const S*>(pop)[((int64_t)lat * 9 + pq) * plane + node]);
     const double w = wgt<double>(q);
     const double scale = lat == 0 ? sd->scale_f : (lat == 1 ? sd->scale_h : sd->scale_g);
     const double qref = lat == 0 ? sd->qref_f : (lat == 1 ? 0.0 : sd->P_ref);
@@ -499,18 +670,21 @@ __global__ __launch_bounds__(WG) void k_decode(const void* pop, const SimDev* sd
 }
 
 template <class S>
-__global__ __launch_bounds__(WG) void k_encode(void* pop, const SimDev* sd, int nlat,
+__global__ __launch_bounds__(WG) void k_encode(void* pop, const SimDev* sd, int nlat, int walls,
                                                const double* in) {
-    const int plane = sd->nx * sd->ny;
+    const int nx = sd->nx, ny = sd->ny, plane = nx * ny;
     const int64_t total = (int64_t)nlat * 9 * plane;
     const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= total) return;
     const int lat = (int)(i / (9 * (int64_t)plane));
     const int q = (int)((i / plane) % 9);
+    const int n = (int)(i % plane);
+    int pq, node;
+    pull_slot(n % nx, n / nx, q, nx, ny, walls != 0, pq, node);
     const double scale = lat == 0 ? sd->scale_f : (lat == 1 ? sd->scale_h : sd->scale_g);
     const double qref = lat == 0 ? sd->qref_f : (lat == 1 ? 0.0 : sd->P_ref);
     const double s = (in[i] * inv_wgt<double>(q) - qref) * scale;
-    static_cast<S*>(pop)[i] = S(s);
+    static_cast<S*>(pop)[((int64_t)lat * 9 + pq) * plane + node] = S(s);
 }
 
 // ---------------------------------------------------------------------------

@@ -33,12 +33,32 @@ namespace cmlb {
 
 enum { FLOW_NONE = 0, FLOW_PRESCRIBED = 1, FLOW_COUPLED = 2 };
 
+// Physical and storage constants of one simulation in the compute type, so
+// kernels read them with scalar loads and never convert on the device.
+template <class T>
+struct PhysConsts {
+    T inv_f, qref_f, inv_h, inv_g;    // storage decode: 1/scale, phi reference
+    T scale_f, scale_h, scale_g;      // storage encode scales (powers of two)
+    T phi_a, phi_b, inv_dphi, phim;   // phase bounds, 1/(phi_a - phi_b), midpoint
+    T theta_k, thetac_k;              // 4/W and 8/W
+    T M_phi, D_s, omega_k, omega_c;   // mobility, diffusivity and their rates
+    T rho_b, drho, nu_b, dnu;         // rho, nu linear in phi
+    T inv_rho_b, omega_nu_b;          // used when drho == 0 / dnu == 0
+    T omega_zeta;
+    T sigma0, beta, c_max, inv_cmax, ks;  // Langmuir isotherm, F_s normalisation
+    T u_wall, Fx, Fy, P_ref;
+    T dr_cs2;                         // cs2 (rho_a - rho_b)/(phi_a - phi_b)
+};
+
 // Per-simulation constants (device memory; read once per workgroup).
 struct SimDev {
     int32_t nx, ny;
     int32_t tile0, ntiles;  // first tile and tile count of this sim
     int64_t off;            // element offset of the sim's population block
     int64_t ushape_off;     // element offset of the prescribed-velocity shapes
+    uint32_t node_base;     // first global node index (random streams)
+    int32_t uniform_rho, uniform_nu;
+    int32_t pad_;
     double W, phi_a, phi_b, inv_dphi, phim;
     double theta_k, thetac_k;  // 4/W and 8/W
     double M_phi, D_s, omega_k, omega_c;
@@ -46,8 +66,10 @@ struct SimDev {
     double sigma0, beta, c_max, ks;
     double u_wall, F_ext_x, F_ext_y, vel_period_T;
     double P_ref;
-    double qref_f;                  // phi reference of the f storage (0 unless FP16)
+    double qref_f;                     // phi reference of the f storage (0 unless FP16)
     double scale_f, scale_h, scale_g;  // storage scales (powers of two)
+    PhysConsts<double> kd;
+    PhysConsts<float> kf;
 };
 
 template <class T>
