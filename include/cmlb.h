@@ -176,6 +176,11 @@ int cmlb_set_use_graph(cmlb_ctx* ctx, int32_t on);
  * dispatch order (0).  Results do not depend on it. */
 int cmlb_set_xcd_remap(cmlb_ctx* ctx, int32_t on);
 
+/* Order in which tiles are handed to workgroups: column groups of `group`
+ * tiles of 64 columns (all tile rows of one group before the next), or 0
+ * for plain row-major order (default).  Results do not depend on it. */
+int cmlb_set_tile_order(cmlb_ctx* ctx, int32_t group);
+
 int64_t cmlb_step_count(const cmlb_ctx* ctx);
 int32_t cmlb_num_sims(const cmlb_ctx* ctx);
 /* Message of the last error on this context (owned by the context). */

@@ -102,6 +102,7 @@ struct cmlb_ctx {
     int tile_rows = 0;          // 0 = default
     int use_graph = 1;
     int xcd_remap = 1;
+    int tile_group = 0;         // column-group width of the tile order (0: row-major)
     bool fault_seen = false;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -206,14 +207,22 @@ void drop_graphs(cmlb_ctx* c) {
     }
 }
 
-std::vector<int4> make_tiles(const cmlb_ctx* c, int rows, std::vector<int>* first,
-                            std::vector<int>* count) {
+// Tile list.  Tiles are visited in column groups of `group` tiles (all
+// rows of group 0, then group 1, ...; row-major inside a group, 0 = one
+// group), so that the tiles a workgroup band has in flight at once form a
+// compact patch whose rows and halos overlap in one L2.
+std::vector<int4> make_tiles(const cmlb_ctx* c, int rows, int group, std::vector<int>* first,
+                             std::vector<int>* count) {
     std::vector<int4> tiles;
     for (int s = 0; s < c->n_sims; ++s) {
         const SimDev& d = c->sims[s];
         if (first) first->push_back((int)tiles.size());
-        for (int y0 = 0; y0 < d.ny; y0 += rows)
-            for (int x0 = 0; x0 < d.nx; x0 += TX) tiles.push_back(make_int4(s, x0, y0, 0));
+        const int tx = (d.nx + TX - 1) / TX;
+        const int g = group > 0 ? group : tx;
+        for (int gx = 0; gx < tx; gx += g)
+            for (int y0 = 0; y0 < d.ny; y0 += rows)
+                for (int t = gx; t < gx + g && t < tx; ++t)
+                    tiles.push_back(make_int4(s, t * TX, y0, 0));
         if (count) count->push_back((int)tiles.size() - first->back());
     }
     return tiles;
@@ -221,7 +230,7 @@ std::vector<int4> make_tiles(const cmlb_ctx* c, int rows, std::vector<int>* firs
 
 int build_tiles(cmlb_ctx* c) {
     std::vector<int> first, count;
-    std::vector<int4> tiles = make_tiles(c, rows_of(c), &first, &count);
+    std::vector<int4> tiles = make_tiles(c, rows_of(c), c->tile_group, &first, &count);
     for (int s = 0; s < c->n_sims; ++s) {
         c->sims[s].tile0 = first[s];
         c->sims[s].ntiles = count[s];
@@ -242,7 +251,7 @@ int build_tiles(cmlb_ctx* c) {
 int build_field_tiles(cmlb_ctx* c) {
     c->ftile0.clear();
     c->fntiles.clear();
-    std::vector<int4> tiles = make_tiles(c, 8, &c->ftile0, &c->fntiles);
+    std::vector<int4> tiles = make_tiles(c, 8, 0, &c->ftile0, &c->fntiles);
     HIP_TRY(c, hipMalloc(&c->d_ftiles, sizeof(int4) * tiles.size()));
     HIP_TRY(c, hipMemcpy(c->d_ftiles, tiles.data(), sizeof(int4) * tiles.size(),
                          hipMemcpyHostToDevice));
@@ -738,6 +747,13 @@ int cmlb_set_xcd_remap(cmlb_ctx* c, int32_t on) {
     c->xcd_remap = on ? 1 : 0;
     drop_graphs(c);
     return CMLB_OK;
+}
+
+int cmlb_set_tile_order(cmlb_ctx* c, int32_t group) {
+    if (!c || group < 0) return CMLB_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->tile_group = group;
+    return build_tiles(c);
 }
 
 int64_t cmlb_step_count(const cmlb_ctx* c) { return c ? c->step : -1; }
