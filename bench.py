@@ -69,11 +69,13 @@ def timed_run(ctx, steps, warmup, torch):
     return start.elapsed_time(end) / 1e3, wall
 
 
-def make_ctx(cmlb, sims, prec, stream, tile_rows=0, graph=True, xcd_remap=True, group=-1):
+def make_ctx(cmlb, sims, prec, stream, tile_rows=0, graph=True, xcd_remap=True, group=-1,
+             stores="auto"):
     ps = [s[0] for s in sims]
     ctx = cmlb.Context(ps, prec, stream=stream)
     if tile_rows:
         ctx.set_tile_rows(tile_rows)
+    ctx.set_store_policy(stores)
     if group >= 0:
         ctx.set_tile_order(group)
     ctx.set_use_graph(graph)
@@ -148,6 +150,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-xcd-remap", action="store_true")
+    ap.add_argument("--stores", default="auto", choices=["auto", "default", "nt"],
+                    help="cache policy of the population stores (default: library's choice)")
     ap.add_argument("--tile-group", type=int, default=-1,
                     help="column-group width of the tile order (default: library's)")
     ap.add_argument("--no-forms", action="store_true", help="skip the other storage forms")
@@ -191,7 +195,7 @@ def main():
     log(f"[bench] workload {args.workload} ({len(sims)} sims, {nodes} nodes), {prec}, "
         f"warmup {args.warmup}, steps {args.steps}")
     ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
-                   not args.no_xcd_remap, args.tile_group)
+                   not args.no_xcd_remap, args.tile_group, args.stores)
     gpu_s, wall_s = timed_run(ctx, args.steps, args.warmup, torch)
     inv = ctx.inventory(0)
     ctx.close()
@@ -252,6 +256,7 @@ def main():
             "graph": not args.no_graph, "tile_rows": args.tile_rows or "default",
             "xcd_remap": not args.no_xcd_remap,
             "tile_group": args.tile_group if args.tile_group >= 0 else "default",
+            "stores": args.stores,
         },
         "roofline": {
             "bound": "hbm",

@@ -176,6 +176,13 @@ int cmlb_set_use_graph(cmlb_ctx* ctx, int32_t on);
  * dispatch order (0).  Results do not depend on it. */
 int cmlb_set_xcd_remap(cmlb_ctx* ctx, int32_t on);
 
+/* Cache policy of the step kernel's population stores: 0 (default) picks
+ * non-temporal stores when the two population buffers together exceed the
+ * GPU's last-level cache (256 MiB on MI355X) and default stores otherwise;
+ * 1 forces default stores, 2 non-temporal stores.  Results do not depend on
+ * it (bitwise). */
+int cmlb_set_store_policy(cmlb_ctx* ctx, int32_t policy);
+
 /* Order in which tiles are handed to workgroups: column groups of `group`
  * tiles of 64 columns (all tile rows of one group before the next), or 0
  * for plain row-major order (default).  Results do not depend on it. */

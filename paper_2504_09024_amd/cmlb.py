@@ -42,7 +42,7 @@ EXPORTS = (
     "cmlb_create", "cmlb_init_fields", "cmlb_step", "cmlb_read_fields", "cmlb_inventory",
     "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_launch_options", "cmlb_set_use_graph",
-    "cmlb_set_xcd_remap", "cmlb_set_tile_order",
+    "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy",
     "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
 )
 
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
     L.cmlb_set_use_graph.argtypes = [vp, ctypes.c_int32]
     L.cmlb_set_xcd_remap.argtypes = [vp, ctypes.c_int32]
     L.cmlb_set_tile_order.argtypes = [vp, ctypes.c_int32]
+    L.cmlb_set_store_policy.argtypes = [vp, ctypes.c_int32]
     L.cmlb_step_count.argtypes = [vp]
     L.cmlb_step_count.restype = ctypes.c_int64
     L.cmlb_num_sims.argtypes = [vp]
@@ -237,6 +238,13 @@ class Context:
 
     def set_use_graph(self, on):
         self._check(self.L.cmlb_set_use_graph(self.h, 1 if on else 0), "cmlb_set_use_graph")
+
+    def set_store_policy(self, policy):
+        """0 auto, 1 default stores, 2 non-temporal stores (or "auto",
+        "default", "nt")."""
+        if isinstance(policy, str):
+            policy = {"auto": 0, "default": 1, "nt": 2}[policy]
+        self._check(self.L.cmlb_set_store_policy(self.h, int(policy)), "cmlb_set_store_policy")
 
     def set_tile_order(self, group):
         self._check(self.L.cmlb_set_tile_order(self.h, int(group)), "cmlb_set_tile_order")

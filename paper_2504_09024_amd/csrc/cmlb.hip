@@ -103,6 +103,8 @@ struct cmlb_ctx {
     int use_graph = 1;
     int xcd_remap = 1;
     int tile_group = 0;         // column-group width of the tile order (0: row-major)
+    int store_policy = 0;       // 0 auto, 1 default stores, 2 non-temporal stores
+    size_t pop_bytes = 0;       // bytes of one population buffer
     bool fault_seen = false;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -160,40 +162,58 @@ bool rows_ok(int prec, int rows) { return shape_of(prec, rows, nullptr); }
 // ------------------------------------------------------------------------
 using StepFn = void (*)(StepArgs);
 
-template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
+template <class S, class T, int FLOW, bool WALLS, bool FIELDS, bool NTS>
 StepFn pick_shape(const Shape& sh) {
     if constexpr (FIELDS) {
-        return k_step<S, T, FLOW, WALLS, 4, 2, true>;
+        return k_step<S, T, FLOW, WALLS, 4, 2, true, false>;
     } else {
-        if (sh.nw == 4 && sh.npt == 1) return k_step<S, T, FLOW, WALLS, 4, 1, false>;
-        if (sh.nw == 4 && sh.npt == 2) return k_step<S, T, FLOW, WALLS, 4, 2, false>;
+        if (sh.nw == 4 && sh.npt == 1) return k_step<S, T, FLOW, WALLS, 4, 1, false, NTS>;
+        if (sh.nw == 4 && sh.npt == 2) return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS>;
         if constexpr (sizeof(T) == 4) {
-            if (sh.nw == 8) return k_step<S, T, FLOW, WALLS, 8, 2, false>;
-            return k_step<S, T, FLOW, WALLS, 16, 2, false>;
+            if (sh.nw == 8) return k_step<S, T, FLOW, WALLS, 8, 2, false, NTS>;
+            return k_step<S, T, FLOW, WALLS, 16, 2, false, NTS>;
         }
-        return k_step<S, T, FLOW, WALLS, 4, 2, false>;
+        return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS>;
     }
 }
-template <class S, class T, bool FIELDS>
-StepFn pick_flow(int flow, int walls, const Shape& sh) {
-    if (flow == FLOW_NONE)
-        return walls ? pick_shape<S, T, FLOW_NONE, true, FIELDS>(sh)
-                     : pick_shape<S, T, FLOW_NONE, false, FIELDS>(sh);
-    if (flow == FLOW_PRESCRIBED)
-        return walls ? pick_shape<S, T, FLOW_PRESCRIBED, true, FIELDS>(sh)
-                     : pick_shape<S, T, FLOW_PRESCRIBED, false, FIELDS>(sh);
-    return walls ? pick_shape<S, T, FLOW_COUPLED, true, FIELDS>(sh)
-                 : pick_shape<S, T, FLOW_COUPLED, false, FIELDS>(sh);
+template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
+StepFn pick_policy(const Shape& sh, bool nts) {
+    if constexpr (FIELDS) return pick_shape<S, T, FLOW, WALLS, true, false>(sh);
+    return nts ? pick_shape<S, T, FLOW, WALLS, false, true>(sh)
+               : pick_shape<S, T, FLOW, WALLS, false, false>(sh);
 }
-StepFn pick_step(int prec, int flow, int walls, const Shape& sh, bool fields) {
+template <class S, class T, bool FIELDS>
+StepFn pick_flow(int flow, int walls, const Shape& sh, bool nts) {
+    if (flow == FLOW_NONE)
+        return walls ? pick_policy<S, T, FLOW_NONE, true, FIELDS>(sh, nts)
+                     : pick_policy<S, T, FLOW_NONE, false, FIELDS>(sh, nts);
+    if (flow == FLOW_PRESCRIBED)
+        return walls ? pick_policy<S, T, FLOW_PRESCRIBED, true, FIELDS>(sh, nts)
+                     : pick_policy<S, T, FLOW_PRESCRIBED, false, FIELDS>(sh, nts);
+    return walls ? pick_policy<S, T, FLOW_COUPLED, true, FIELDS>(sh, nts)
+                 : pick_policy<S, T, FLOW_COUPLED, false, FIELDS>(sh, nts);
+}
+StepFn pick_step(int prec, int flow, int walls, const Shape& sh, bool fields, bool nts) {
     if (prec == CMLB_FP64)
-        return fields ? pick_flow<double, double, true>(flow, walls, sh)
-                      : pick_flow<double, double, false>(flow, walls, sh);
+        return fields ? pick_flow<double, double, true>(flow, walls, sh, false)
+                      : pick_flow<double, double, false>(flow, walls, sh, nts);
     if (prec == CMLB_FP32)
-        return fields ? pick_flow<float, float, true>(flow, walls, sh)
-                      : pick_flow<float, float, false>(flow, walls, sh);
-    return fields ? pick_flow<_Float16, float, true>(flow, walls, sh)
-                  : pick_flow<_Float16, float, false>(flow, walls, sh);
+        return fields ? pick_flow<float, float, true>(flow, walls, sh, false)
+                      : pick_flow<float, float, false>(flow, walls, sh, nts);
+    return fields ? pick_flow<_Float16, float, true>(flow, walls, sh, false)
+                  : pick_flow<_Float16, float, false>(flow, walls, sh, nts);
+}
+
+// Population stores bypass-allocate (non-temporal) when the two population
+// buffers together exceed the GPU's last-level (Infinity) cache, 256 MiB on
+// MI355X: such lattices are re-read from HBM every step anyway, and streaming
+// the stores keeps the L2 for the lines that neighbouring tiles share.
+// Smaller lattices keep default stores, so the next step finds them cached.
+constexpr size_t LLC_BYTES = size_t(256) << 20;
+bool stores_nt(const cmlb_ctx* c) {
+    if (c->store_policy == 1) return false;
+    if (c->store_policy == 2) return true;
+    return 2 * c->pop_bytes > LLC_BYTES;
 }
 
 int rows_of(const cmlb_ctx* c) { return c->tile_rows ? c->tile_rows : default_rows(c->prec); }
@@ -287,7 +307,7 @@ int step_grid(const cmlb_ctx* c) { return c->xcd_remap ? (c->ntiles + 7) / 8 * 8
 
 int launch_step(cmlb_ctx* c, int parity) {
     const Shape sh = shape_cur(c);
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, sh, false);
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, sh, false, stores_nt(c));
     StepArgs a = step_args(c, parity);
     hipLaunchKernelGGL(fn, dim3(step_grid(c)), dim3(sh.nw * 64), 0, c->stream, a);
     HIP_TRY(c, hipGetLastError());
@@ -297,7 +317,7 @@ int launch_step(cmlb_ctx* c, int parity) {
 // Graph of 2*GRAPH_PAIRS steps starting from parity p (ends at parity p).
 int build_graph(cmlb_ctx* c, int p) {
     const Shape sh = shape_cur(c);
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, sh, false);
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, sh, false, stores_nt(c));
     HIP_TRY(c, hipGraphCreate(&c->graph[p], 0));
     hipGraphNode_t prev = nullptr;
     for (int k = 0; k < 2 * GRAPH_PAIRS; ++k) {
@@ -510,6 +530,7 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
     }
     const size_t sb = storage_bytes(precision);
     const size_t tb = precision == CMLB_FP64 ? 8 : 4;
+    c->pop_bytes = sb * off;
     if (hipMalloc(&c->pop[0], sb * off) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->pop[1], sb * off) != hipSuccess) return bail(CMLB_ENOMEM);
     if (uoff && hipMalloc(&c->ushape, tb * uoff) != hipSuccess) return bail(CMLB_ENOMEM);
@@ -613,7 +634,7 @@ int cmlb_read_fields(cmlb_ctx* c, int32_t sim, double* phi, double* cc, double* 
     const SimDev& d = c->sims[sim];
     const int64_t plane = (int64_t)d.nx * d.ny;
     const Shape fsh{8, 4, 2};
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, fsh, true);
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, fsh, true, false);
     StepArgs a = step_args(c, c->cur);
     a.dst = nullptr;
     a.step_out = nullptr;
@@ -745,6 +766,14 @@ int cmlb_set_xcd_remap(cmlb_ctx* c, int32_t on) {
     if (!c) return CMLB_EINVAL;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->xcd_remap = on ? 1 : 0;
+    drop_graphs(c);
+    return CMLB_OK;
+}
+
+int cmlb_set_store_policy(cmlb_ctx* c, int32_t policy) {
+    if (!c || policy < 0 || policy > 2) return CMLB_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->store_policy = policy;
     drop_graphs(c);
     return CMLB_OK;
 }

@@ -67,6 +67,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
 }
 
+// Stores take a cache policy CP: 0 = default, CPOL_NT = non-temporal
+// (streamed past the caches rather than kept in them).
+constexpr int CPOL_NT = 2;
+
 template <class S>
 struct Buf;
 template <>
@@ -74,9 +78,10 @@ struct Buf<double> {
     static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
     }
+    template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, double v,
                                                  uint32_t) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, CP);
     }
 };
 template <>
@@ -84,9 +89,10 @@ struct Buf<float> {
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
+    template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
                                                  uint32_t) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, CP);
     }
 };
 // binary16 storage: loads widen exactly; stores round stochastically with
@@ -100,10 +106,12 @@ struct Buf<_Float16> {
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)));
     }
+    template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
                                                  uint32_t rnd) {
         const h16x2 h = __builtin_amdgcn_cvt_sr_f16_f32(h16x2{}, v, rnd, false);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, so,
+                                              CP);
     }
 };
 
@@ -199,7 +207,10 @@ __device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int pb, int
                 sy = sy < 0 ? sy + ny : sy - ny;
             }
         }
-        v[a] = T(Buf<S>::load(r, (sy * nx + sx) * (int)sizeof(S), pa * pb));
+        // the plane varies per lane here (bounce-back), so its offset goes
+        // into the vector offset: a per-lane scalar offset would make the
+        // compiler loop over the distinct values
+        v[a] = T(Buf<S>::load(r, (sy * nx + sx) * (int)sizeof(S) + pa * pb, 0));
     }
 }
 
@@ -261,8 +272,11 @@ struct Occupancy {
     static constexpr int waves_per_eu = sizeof(T) == 4 ? 4 : (NW >= 8 ? 2 : 2);
 };
 
-template <class S, class T, int FLOW, bool WALLS, int NW, int NPT, bool FIELDS>
+// NTS: population stores non-temporal (for lattices too large to stay in the
+// last-level cache between steps).
+template <class S, class T, int FLOW, bool WALLS, int NW, int NPT, bool FIELDS, bool NTS>
 __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_step(const StepArgs a) {
+    constexpr int CP = NTS ? CPOL_NT : 0;
     constexpr int NT = NW * 64;
     constexpr bool CPL = FLOW == FLOW_COUPLED;
     constexpr bool MOV = FLOW != FLOW_NONE;
@@ -551,12 +565,12 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
                     const int so_q = q * pb;
-                    Buf<S>::store(wF, vo, so_q, qf[j][q], rs + weyl(3 * q));
-                    Buf<S>::store(wH, vo, so_q, qh[j][q], rs + weyl(3 * q + 1));
+                    Buf<S>::template store<CP>(wF, vo, so_q, qf[j][q], rs + weyl(3 * q));
+                    Buf<S>::template store<CP>(wH, vo, so_q, qh[j][q], rs + weyl(3 * q + 1));
                     if constexpr (CPL) {
                         T v = qg[j][q];
                         if (WALLS && wdir != 0 && EYa(q) == wdir) v += wcorr * T(EXa(q));
-                        Buf<S>::store(wG, vo, so_q, v, rs + weyl(3 * q + 2));
+                        Buf<S>::template store<CP>(wG, vo, so_q, v, rs + weyl(3 * q + 2));
                     }
                 }
             }

@@ -176,6 +176,22 @@ def test_tile_shapes_bitwise_fp64(gpu_lib):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_store_policy_bitwise(gpu_lib, prec):
+    """Default and non-temporal population stores give identical results."""
+    p, fl = W.random_fields(150, 45, seed=8, amp=1.0, sigma0=2e-3, beta=0.3, u_wall=2e-2,
+                            M_phi=0.04)
+    outs = []
+    for policy in ("default", "nt"):
+        ctx = gpu_ctx(p, fl, prec)
+        ctx.set_store_policy(policy)
+        ctx.step(30)
+        outs.append(ctx.get_populations(0))
+        ctx.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_graph_matches_direct_launch(gpu_lib, prec):
     p, fl = W.shear_drop(nx=192, ny=64, R=10.0)
