@@ -102,6 +102,60 @@ def traffic_entry(workload_key, prec):
     return ent.get("bytes_per_launch")
 
 
+def _counter_kib(csv_path, counter, kernel_substr):
+    """Mean per-dispatch value of `counter` over the dispatches of kernels
+    whose name contains `kernel_substr` in a rocprofv3 counter_collection.csv
+    (values of one dispatch summed over their instances)."""
+    import csv
+    per = {}
+    with open(csv_path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter or kernel_substr not in r["Kernel_Name"]:
+                continue
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    if not per:
+        raise ValueError(f"no {counter} rows for '{kernel_substr}' in {csv_path}")
+    return sum(per.values()) / len(per), len(per)
+
+
+def record_traffic(key, nodes, prec, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv,
+                   copy_bytes, path=None):
+    """Scale the step kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
+    what the same counters read for a plain device copy of copy_bytes, and
+    store HBM bytes per launch under `key` in profiles/traffic.json, tagged
+    with the hash of the kernel sources."""
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
+    cf, _ = _counter_kib(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _counter_kib(copy_write_csv, "WRITE_SIZE", "copyBuffer")
+    fetch_scale = copy_bytes / (cf * 1024.0)
+    write_scale = copy_bytes / (cw * 1024.0)
+    kf, nf = _counter_kib(fetch_csv, "FETCH_SIZE", "k_step")
+    kw, nw = _counter_kib(write_csv, "WRITE_SIZE", "k_step")
+    fetch = kf * 1024.0 * fetch_scale
+    write = kw * 1024.0 * write_scale
+    alg = algorithmic_bytes_per_node(prec) * nodes
+    data = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            data = json.load(fh)
+    data["_note"] = ("HBM-side bytes per step-kernel launch from rocprofv3 --pmc FETCH_SIZE and "
+                     "WRITE_SIZE (KiB per dispatch), each scaled by the counter's reading for a "
+                     "plain device copy (bench.py --copy-calibration).")
+    data["calibration"] = {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": round(cf, 2),
+                           "WRITE_SIZE_KiB": round(cw, 2), "fetch_scale": fetch_scale,
+                           "write_scale": write_scale}
+    data[key] = {"kernel_hash": kernel_hash(), "bytes_per_launch": int(round(fetch + write)),
+                 "fetch_bytes": int(round(fetch)), "write_bytes": int(round(write)),
+                 "algorithmic_bytes": alg,
+                 "traffic_over_algorithmic": round((fetch + write) / alg, 4),
+                 "fetch_over_algorithmic_reads": round(fetch / (alg / 2), 4),
+                 "dispatches": [nf, nw]}
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1)
+        fh.write("\n")
+    return data[key]
+
+
 def cpu_baseline(sims, target_s=10.0):
     """The FP64 oracle on a bounded sample of the workload: the first
     simulation of the set, as many steps as fit ~target_s (at least 2)."""
@@ -159,7 +213,22 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--record-traffic", nargs=4, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="(no GPU) turn rocprofv3 counter_collection.csv files of the step "
+                         "kernel (--workload/--precision) and of the copy calibration into "
+                         "profiles/traffic.json")
     args = ap.parse_args()
+
+    if args.record_traffic:
+        from paper_2504_09024_amd import workloads as W
+        sims, _ = workload(W, args.workload)
+        nodes = sum(p["nx"] * p["ny"] for p, _ in sims)
+        ent = record_traffic(f"{args.workload}:{args.precision}", nodes, args.precision,
+                             *args.record_traffic,
+                             copy_bytes=(args.copy_calibration or 1024) << 20)
+        print(json.dumps(ent))
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
