@@ -119,7 +119,7 @@ def _counter_kib(csv_path, counter, kernel_substr):
 
 
 def record_traffic(key, nodes, prec, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv,
-                   copy_bytes, path=None):
+                   copy_bytes, path=None, lattices=3):
     """Scale the step kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
     what the same counters read for a plain device copy of copy_bytes, and
     store HBM bytes per launch under `key` in profiles/traffic.json, tagged
@@ -133,7 +133,7 @@ def record_traffic(key, nodes, prec, fetch_csv, write_csv, copy_fetch_csv, copy_
     kw, nw = _counter_kib(write_csv, "WRITE_SIZE", "k_step")
     fetch = kf * 1024.0 * fetch_scale
     write = kw * 1024.0 * write_scale
-    alg = algorithmic_bytes_per_node(prec) * nodes
+    alg = algorithmic_bytes_per_node(prec, lattices) * nodes
     data = {}
     if os.path.exists(path):
         with open(path) as fh:
@@ -181,17 +181,41 @@ def cpu_baseline(sims, target_s=12.0):
                       f"coupled, {dt:.1f} s, FP64, OpenMP over rows)"}
 
 
+WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2")
+
+
 def workload(W, name):
     if name == "batched":
         sims = W.batched_shear_drops(64)
         desc = ("64 seeded coupled surfactant-laden shear drops (default_rng(2504)): sizes "
                 "256x256..1024x512, R=ny/8, Ca~U[0.05,0.6], E~U[0.1,0.5], c0~U[0.1,0.5], "
                 "Pe_s log-U[0.5,10], Re=0.1, Pe*=0.5, walls at +-U0; one launch per step")
-    else:
+    elif name == "c3":
         sims = [W.shear_drop()]
         desc = ("coupled surfactant-laden shear drop, 1024x512, R=64, Ca=0.3, E=0.2, "
                 "c0/c_max=0.3, Re=0.1, walls at +-U0")
+    elif name == "c1":
+        sims = [W.static_drop()]
+        desc = "static drop, 128x128 periodic, R=32, W=4, D_s=0.01, phi and c lattices"
+    elif name == "c2":
+        sims = [W.vortex_drop()]
+        desc = ("drop in a time-reversing single vortex, 512x512 periodic, R=64, U0=0.02, "
+                "T=20000, phi and c lattices")
+    elif name == "e1":
+        sims = [W.static_drop(n=512, R=128.0, D_s=d) for d in (0.05, 0.1, 0.2)]
+        desc = ("three static drops (Sec. 4.1), 512x512 periodic, R=128, W=4, "
+                "D_s in {0.05, 0.1, 0.2}, phi and c lattices, one launch per step")
+    elif name == "e2":
+        sims = [W.advected_drop()]
+        desc = ("drop in a uniform flow (Sec. 4.2), 1024x512 periodic, R=128, D_s=0.1, "
+                "U0=512/T_D, phi and c lattices")
+    else:
+        raise ValueError(name)
     return sims, desc
+
+
+def lattices_of(sims):
+    return 3 if sims[0][0].get("flow") == "coupled" else 2
 
 
 def main():
@@ -200,7 +224,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
-    ap.add_argument("--workload", default="batched", choices=["batched", "c3"])
+    ap.add_argument("--workload", default="batched", choices=list(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-xcd-remap", action="store_true")
@@ -226,7 +250,8 @@ def main():
         nodes = sum(p["nx"] * p["ny"] for p, _ in sims)
         ent = record_traffic(f"{args.workload}:{args.precision}", nodes, args.precision,
                              *args.record_traffic,
-                             copy_bytes=(args.copy_calibration or 1024) << 20)
+                             copy_bytes=(args.copy_calibration or 1024) << 20,
+                             lattices=lattices_of(sims))
         print(json.dumps(ent))
         return
 
@@ -270,7 +295,8 @@ def main():
     ctx.close()
     mlups = nodes * args.steps / gpu_s / 1e6
     ms_per_step = gpu_s * 1e3 / args.steps
-    bpl = algorithmic_bytes_per_node(prec) * nodes
+    lat = lattices_of(sims)
+    bpl = algorithmic_bytes_per_node(prec, lat) * nodes
     achieved = bpl / (gpu_s / args.steps) / 1e9
     log(f"[bench] {mlups:.0f} MLUPS, {ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s "
         f"({achieved / HBM_PEAK_GBS:.3f} of peak; wall {wall_s:.3f} s)")
@@ -321,7 +347,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc,
-            "sims": len(sims), "nodes": nodes, "storage": prec, "lattices": 3,
+            "sims": len(sims), "nodes": nodes, "storage": prec, "lattices": lat,
             "graph": not args.no_graph, "tile_rows": args.tile_rows or "default",
             "xcd_remap": not args.no_xcd_remap,
             "tile_group": args.tile_group if args.tile_group >= 0 else "default",

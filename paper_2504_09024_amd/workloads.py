@@ -80,6 +80,22 @@ def static_drop(n=128, R=32.0, W=4.0, D_s=0.01, M_phi=0.1, mode=1, center=None):
     return p, dict(phi=phi, c=c)
 
 
+def advected_drop(Lo=512, R=None, W=4.0, D_s=0.1, M_phi=0.1, center=None):
+    """Drop carried by a uniform flow along x on a periodic 2 Lo x Lo box
+    (Sec. 4.2 set-up): R = Lo/4, c_hat = (1 - cos theta)/2, and U0 chosen so
+    that the drop travels exactly Lo in T_D = R^2/D_s steps.  The velocity
+    is a prescribed steady field (vel_period_T = 0)."""
+    R = Lo / 4.0 if R is None else float(R)
+    nx, ny = 2 * Lo, Lo
+    T_D = R * R / D_s
+    U0 = Lo / T_D
+    p = params(nx=nx, ny=ny, bc_y="periodic", flow="prescribed", W=W, D_s=D_s, M_phi=M_phi,
+               vel_period_T=0.0)
+    xc, yc = center if center is not None else (Lo / 2.0, Lo / 2.0)
+    phi, c = drop_fields(nx, ny, xc, yc, R, W, lambda th: 0.5 * (1.0 - np.cos(th)))
+    return p, dict(phi=phi, c=c, ux=np.full((ny, nx), U0), uy=np.zeros((ny, nx)))
+
+
 def vortex_drop(n=512, R=64.0, W=4.0, U0=0.02, T=20000.0, D_s=0.01, M_phi=0.1,
                 center=None, c_hat=0.5):
     """Drop in a prescribed time-reversing single vortex on a periodic box.

@@ -31,9 +31,15 @@ CASES = {
                                               bc_y="periodic"), 150),
     # 1024x512 coupled shear drop of the benchmark (Ca = 0.3, E = 0.2, c0 = 0.3)
     "c3_full": (lambda: W.shear_drop(), 20),
+    # 512x512 single vortex at full size.  Only 4 steps: inside this large
+    # drop phi sits within ~1e-11 of phi_a, where the regularised normal is
+    # still a unit vector and the sharpening flux amplifies rounding-level
+    # differences about 2.3x per step (the oracle turns a 1e-16 perturbation
+    # into 3e-12 after 10 steps and 7e-8 after 60)
+    "c2_full": (lambda: W.vortex_drop(center=(256.3, 383.6)), 4),
 }
 
 # cases compared against the FP64 bar (1e-12) and cheap enough for the CPU
 # conditioning check
 FP64_CONDITIONING = ["ragged_periodic", "vortex", "shear_drop", "coupled_random",
-                     "density_ratio", "c3_full"]
+                     "density_ratio", "c3_full", "c2_full"]

@@ -1,0 +1,43 @@
+"""Interface profile of the surfactant, c_hat(theta), read off a field.
+
+For the equilibrium profiles (Eqs. CACEeq and ISSeq) with phi_a = 1,
+phi_b = 0: c = c_hat(theta) sech^2(2 zeta/W) and 4 phi (1 - phi) =
+sech^2(2 zeta/W), so within an angular bin c_hat is the ratio of the bin's
+sums of c and of 4 phi (1 - phi) over the interface band.  Sec. 4.1 gives the
+closed form for the static drop, c_hat = (1 - exp(-D_s t/R^2) cos theta)/2."""
+import numpy as np
+
+
+def polar(nx, ny, xc, yc):
+    x = np.arange(nx, dtype=np.float64)[None, :] - xc
+    y = np.arange(ny, dtype=np.float64)[:, None] - yc
+    return np.hypot(x, y), np.arctan2(y, x)
+
+
+def interface_chat(phi, c, xc, yc, nbins=72, band=0.05, periodic_x=None):
+    """(theta_centres, c_hat) over `nbins` equal angular bins around
+    (xc, yc); nodes whose 4 phi (1 - phi) is below `band` are left out.
+    `periodic_x`: box length for taking x offsets to the nearest image."""
+    ny, nx = phi.shape
+    x = np.arange(nx, dtype=np.float64)[None, :] - xc
+    if periodic_x:
+        x = (x + periodic_x / 2.0) % periodic_x - periodic_x / 2.0
+    y = np.arange(ny, dtype=np.float64)[:, None] - yc
+    th = np.broadcast_to(np.arctan2(y, x), phi.shape)
+    w = 4.0 * phi * (1.0 - phi)
+    m = w > band
+    k = np.minimum(((th[m] + np.pi) / (2 * np.pi) * nbins).astype(int), nbins - 1)
+    num = np.bincount(k, weights=c[m], minlength=nbins)
+    den = np.bincount(k, weights=w[m], minlength=nbins)
+    centres = -np.pi + (np.arange(nbins) + 0.5) * 2 * np.pi / nbins
+    return centres, num / den
+
+
+def chat_exact(theta, t_star, nbins=None):
+    """Sec. 4.1 closed form; with `nbins`, cos theta is averaged over each
+    bin (factor sin(h)/h, h = pi/nbins)."""
+    f = 1.0
+    if nbins:
+        h = np.pi / nbins
+        f = np.sin(h) / h
+    return 0.5 * (1.0 - np.exp(-t_star) * f * np.cos(theta))

@@ -67,6 +67,7 @@ PARITY = [
     ("shear_drop", "fp64"), ("shear_drop", "fp32"),
     ("coupled_random", "fp64"),
     ("density_ratio", "fp64"),
+    ("c2_full", "fp64"), ("c2_full", "fp32"),
 ]
 
 
