@@ -70,11 +70,11 @@ def timed_run(ctx, steps, warmup, torch):
 
 
 def make_ctx(cmlb, sims, prec, stream, tile_rows=0, graph=True, xcd_remap=True, group=-1,
-             stores="auto"):
+             stores="auto", tile_width=0):
     ps = [s[0] for s in sims]
     ctx = cmlb.Context(ps, prec, stream=stream)
     if tile_rows:
-        ctx.set_tile_rows(tile_rows)
+        ctx.set_tile_shape(tile_width or 64, tile_rows)
     ctx.set_store_policy(stores)
     if group >= 0:
         ctx.set_tile_order(group)
@@ -226,6 +226,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
     ap.add_argument("--workload", default="batched", choices=list(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--tile-width", type=int, default=0, help="64 or 128 (with --tile-rows)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-xcd-remap", action="store_true")
     ap.add_argument("--stores", default="auto", choices=["auto", "default", "nt"],
@@ -289,7 +290,7 @@ def main():
     log(f"[bench] workload {args.workload} ({len(sims)} sims, {nodes} nodes), {prec}, "
         f"warmup {args.warmup}, steps {args.steps}")
     ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
-                   not args.no_xcd_remap, args.tile_group, args.stores)
+                   not args.no_xcd_remap, args.tile_group, args.stores, args.tile_width)
     gpu_s, wall_s = timed_run(ctx, args.steps, args.warmup, torch)
     inv = ctx.inventory(0)
     ctx.close()
@@ -349,6 +350,7 @@ def main():
             "workload": desc,
             "sims": len(sims), "nodes": nodes, "storage": prec, "lattices": lat,
             "graph": not args.no_graph, "tile_rows": args.tile_rows or "default",
+            "tile_width": args.tile_width or "default",
             "xcd_remap": not args.no_xcd_remap,
             "tile_group": args.tile_group if args.tile_group >= 0 else "default",
             "stores": args.stores,

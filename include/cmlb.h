@@ -159,13 +159,16 @@ int cmlb_fault_flags(cmlb_ctx* ctx, int32_t sim, int32_t* flags);
  * CMLB_ERANGE if any fault flag is set. */
 int cmlb_synchronize(cmlb_ctx* ctx);
 
-/* Launch configuration of the step kernel: rows per workgroup tile
- * (tile = 64 x rows nodes).  Accepted values are listed by
- * cmlb_launch_options; 0 restores the default.  Results in FP64 do not
- * depend on it (bitwise). */
+/* Launch configuration of the step kernel: the workgroup tile is width x
+ * rows nodes (width 64: one wavefront across x; 128: two).  Accepted pairs
+ * are listed by cmlb_launch_options; (0, 0) restores the default.  Results
+ * in FP64 do not depend on it (bitwise).  cmlb_set_tile_rows(ctx, r) is
+ * cmlb_set_tile_shape(ctx, 64, r) (r = 0: the default). */
+int cmlb_set_tile_shape(cmlb_ctx* ctx, int32_t width, int32_t rows);
 int cmlb_set_tile_rows(cmlb_ctx* ctx, int32_t rows);
-/* Writes up to `cap` accepted tile-row values into rows[], returns how many. */
-int cmlb_launch_options(const cmlb_ctx* ctx, int32_t* rows, int32_t cap);
+/* Writes up to cap/2 accepted (width, rows) pairs into shapes[] as
+ * consecutive int32 pairs; returns how many pairs the precision has. */
+int cmlb_launch_options(const cmlb_ctx* ctx, int32_t* shapes, int32_t cap);
 
 /* Capture the step loop in a HIP graph (1) or launch kernels directly (0).
  * Default 1.  Results do not depend on it. */

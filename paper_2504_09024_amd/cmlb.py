@@ -41,7 +41,8 @@ class SimParams(ctypes.Structure):
 EXPORTS = (
     "cmlb_create", "cmlb_init_fields", "cmlb_step", "cmlb_read_fields", "cmlb_inventory",
     "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
-    "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_launch_options", "cmlb_set_use_graph",
+    "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
+    "cmlb_set_use_graph",
     "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy",
     "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
 )
@@ -79,6 +80,7 @@ def load(path: str = LIB_PATH):
     L.cmlb_fault_flags.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.cmlb_synchronize.argtypes = [vp]
     L.cmlb_set_tile_rows.argtypes = [vp, ctypes.c_int32]
+    L.cmlb_set_tile_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.cmlb_launch_options.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.cmlb_set_use_graph.argtypes = [vp, ctypes.c_int32]
     L.cmlb_set_xcd_remap.argtypes = [vp, ctypes.c_int32]
@@ -231,10 +233,15 @@ class Context:
     def set_tile_rows(self, rows):
         self._check(self.L.cmlb_set_tile_rows(self.h, int(rows)), "cmlb_set_tile_rows")
 
+    def set_tile_shape(self, width, rows):
+        self._check(self.L.cmlb_set_tile_shape(self.h, int(width), int(rows)),
+                    "cmlb_set_tile_shape")
+
     def launch_options(self):
-        buf = (ctypes.c_int32 * 16)()
-        n = self.L.cmlb_launch_options(self.h, buf, 16)
-        return [buf[i] for i in range(max(n, 0))]
+        """Accepted (width, rows) tile shapes."""
+        buf = (ctypes.c_int32 * 64)()
+        n = self.L.cmlb_launch_options(self.h, buf, 64)
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(max(n, 0))]
 
     def set_use_graph(self, on):
         self._check(self.L.cmlb_set_use_graph(self.h, 1 if on else 0), "cmlb_set_use_graph")

@@ -100,6 +100,7 @@ struct cmlb_ctx {
     int cur = 0;                // population/counter parity holding the current state
     int64_t step = 0;
     int tile_rows = 0;          // 0 = default
+    int tile_w = 0;             // 0 = default
     int use_graph = 1;
     int xcd_remap = 1;
     int tile_group = 0;         // column-group width of the tile order (0: row-major)
@@ -132,30 +133,39 @@ int fail(cmlb_ctx* c, int code, const char* fmt, ...) {
             return fail((ctx), CMLB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// Launch shapes of the step kernel: tile = 64 x rows, rows = waves * rows per
-// thread.  FP64 keeps 4-wave workgroups (its registers allow two waves per
-// SIMD); the FP32-arithmetic forms also offer 8- and 16-wave workgroups at two
-// rows per thread (four waves per SIMD), whose taller tiles share more halo.
+// Launch shapes of the step kernel: tile = width x rows, width = 64 per
+// wavefront across x, rows = (waves / wavefronts across) * rows per thread.
+// FP64 keeps 4-wave workgroups (its registers allow two waves per SIMD); the
+// FP32-arithmetic forms also offer 8- and 16-wave workgroups at two rows per
+// thread (four waves per SIMD).  128-column tiles fetch fewer partly-used
+// cache lines at their x edges.
 struct Shape {
-    int rows, nw, npt;
+    int width, rows, nw, npt, wx;  // tile = width x rows; nw waves, wx of them across x
 };
-const Shape SHAPES_64[] = {{4, 4, 1}, {8, 4, 2}};
-const Shape SHAPES_32[] = {{4, 4, 1}, {8, 4, 2}, {16, 8, 2}, {32, 16, 2}};
+const Shape SHAPES_64[] = {{64, 4, 4, 1, 1}, {64, 8, 4, 2, 1}, {128, 4, 4, 2, 2}};
+const Shape SHAPES_32[] = {{64, 4, 4, 1, 1},   {64, 8, 4, 2, 1},   {64, 16, 8, 2, 1},
+                           {64, 32, 16, 2, 1}, {128, 8, 8, 2, 2},  {128, 16, 16, 2, 2}};
+constexpr int N_SHAPES_64 = sizeof(SHAPES_64) / sizeof(Shape);
+constexpr int N_SHAPES_32 = sizeof(SHAPES_32) / sizeof(Shape);
 
-int default_rows(int prec) { return prec == CMLB_FP64 ? 8 : 16; }
+// the field-evaluation kernel's fixed launch: 64 x 8 tiles of 4 waves
+constexpr int FIELD_NW = 4, FIELD_NPT = 2, FIELD_ROWS = FIELD_NW * FIELD_NPT;
 
-bool shape_of(int prec, int rows, Shape* out) {
+// defaults measured on the 64-drop batch: FP64 64x8 (4 waves), FP32/FP16
+// 128x8 (8 waves, two across x)
+int default_width(int prec) { return prec == CMLB_FP64 ? 64 : 128; }
+int default_rows(int) { return 8; }
+
+bool shape_of(int prec, int width, int rows, Shape* out) {
     const Shape* t = prec == CMLB_FP64 ? SHAPES_64 : SHAPES_32;
-    const int n = prec == CMLB_FP64 ? 2 : 4;
+    const int n = prec == CMLB_FP64 ? N_SHAPES_64 : N_SHAPES_32;
     for (int i = 0; i < n; ++i)
-        if (t[i].rows == rows) {
+        if (t[i].width == width && t[i].rows == rows) {
             if (out) *out = t[i];
             return true;
         }
     return false;
 }
-
-bool rows_ok(int prec, int rows) { return shape_of(prec, rows, nullptr); }
 
 // ------------------------------------------------------------------------
 // kernel selection
@@ -165,15 +175,22 @@ using StepFn = void (*)(StepArgs);
 template <class S, class T, int FLOW, bool WALLS, bool FIELDS, bool NTS>
 StepFn pick_shape(const Shape& sh) {
     if constexpr (FIELDS) {
-        return k_step<S, T, FLOW, WALLS, 4, 2, true, false>;
+        return k_step<S, T, FLOW, WALLS, FIELD_NW, FIELD_NPT, true, false, 1>;
     } else {
-        if (sh.nw == 4 && sh.npt == 1) return k_step<S, T, FLOW, WALLS, 4, 1, false, NTS>;
-        if (sh.nw == 4 && sh.npt == 2) return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS>;
-        if constexpr (sizeof(T) == 4) {
-            if (sh.nw == 8) return k_step<S, T, FLOW, WALLS, 8, 2, false, NTS>;
-            return k_step<S, T, FLOW, WALLS, 16, 2, false, NTS>;
+        if (sh.wx == 1) {
+            if (sh.nw == 4 && sh.npt == 1) return k_step<S, T, FLOW, WALLS, 4, 1, false, NTS, 1>;
+            if (sh.nw == 4 && sh.npt == 2) return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS, 1>;
+            if constexpr (sizeof(T) == 4) {
+                if (sh.nw == 8) return k_step<S, T, FLOW, WALLS, 8, 2, false, NTS, 1>;
+                return k_step<S, T, FLOW, WALLS, 16, 2, false, NTS, 1>;
+            }
+            return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS, 1>;
         }
-        return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS>;
+        if constexpr (sizeof(T) == 4) {
+            if (sh.nw == 8) return k_step<S, T, FLOW, WALLS, 8, 2, false, NTS, 2>;
+            return k_step<S, T, FLOW, WALLS, 16, 2, false, NTS, 2>;
+        }
+        return k_step<S, T, FLOW, WALLS, 4, 2, false, NTS, 2>;
     }
 }
 template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
@@ -217,6 +234,7 @@ bool stores_nt(const cmlb_ctx* c) {
 }
 
 int rows_of(const cmlb_ctx* c) { return c->tile_rows ? c->tile_rows : default_rows(c->prec); }
+int width_of(const cmlb_ctx* c) { return c->tile_w ? c->tile_w : default_width(c->prec); }
 
 void drop_graphs(cmlb_ctx* c) {
     for (int i = 0; i < 2; ++i) {
@@ -231,18 +249,18 @@ void drop_graphs(cmlb_ctx* c) {
 // rows of group 0, then group 1, ...; row-major inside a group, 0 = one
 // group), so that the tiles a workgroup band has in flight at once form a
 // compact patch whose rows and halos overlap in one L2.
-std::vector<int4> make_tiles(const cmlb_ctx* c, int rows, int group, std::vector<int>* first,
-                             std::vector<int>* count) {
+std::vector<int4> make_tiles(const cmlb_ctx* c, int width, int rows, int group,
+                             std::vector<int>* first, std::vector<int>* count) {
     std::vector<int4> tiles;
     for (int s = 0; s < c->n_sims; ++s) {
         const SimDev& d = c->sims[s];
         if (first) first->push_back((int)tiles.size());
-        const int tx = (d.nx + TX - 1) / TX;
+        const int tx = (d.nx + width - 1) / width;
         const int g = group > 0 ? group : tx;
         for (int gx = 0; gx < tx; gx += g)
             for (int y0 = 0; y0 < d.ny; y0 += rows)
                 for (int t = gx; t < gx + g && t < tx; ++t)
-                    tiles.push_back(make_int4(s, t * TX, y0, 0));
+                    tiles.push_back(make_int4(s, t * width, y0, 0));
         if (count) count->push_back((int)tiles.size() - first->back());
     }
     return tiles;
@@ -250,7 +268,8 @@ std::vector<int4> make_tiles(const cmlb_ctx* c, int rows, int group, std::vector
 
 int build_tiles(cmlb_ctx* c) {
     std::vector<int> first, count;
-    std::vector<int4> tiles = make_tiles(c, rows_of(c), c->tile_group, &first, &count);
+    std::vector<int4> tiles =
+        make_tiles(c, width_of(c), rows_of(c), c->tile_group, &first, &count);
     for (int s = 0; s < c->n_sims; ++s) {
         c->sims[s].tile0 = first[s];
         c->sims[s].ntiles = count[s];
@@ -271,7 +290,7 @@ int build_tiles(cmlb_ctx* c) {
 int build_field_tiles(cmlb_ctx* c) {
     c->ftile0.clear();
     c->fntiles.clear();
-    std::vector<int4> tiles = make_tiles(c, 8, 0, &c->ftile0, &c->fntiles);
+    std::vector<int4> tiles = make_tiles(c, 64, FIELD_ROWS, 0, &c->ftile0, &c->fntiles);
     HIP_TRY(c, hipMalloc(&c->d_ftiles, sizeof(int4) * tiles.size()));
     HIP_TRY(c, hipMemcpy(c->d_ftiles, tiles.data(), sizeof(int4) * tiles.size(),
                          hipMemcpyHostToDevice));
@@ -279,8 +298,8 @@ int build_field_tiles(cmlb_ctx* c) {
 }
 
 Shape shape_cur(const cmlb_ctx* c) {
-    Shape sh{8, 4, 2};
-    shape_of(c->prec, rows_of(c), &sh);
+    Shape sh{64, 8, 4, 2, 1};
+    shape_of(c->prec, width_of(c), rows_of(c), &sh);
     return sh;
 }
 
@@ -633,8 +652,7 @@ int cmlb_read_fields(cmlb_ctx* c, int32_t sim, double* phi, double* cc, double* 
     if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
     const SimDev& d = c->sims[sim];
     const int64_t plane = (int64_t)d.nx * d.ny;
-    const Shape fsh{8, 4, 2};
-    StepFn fn = pick_step(c->prec, c->flow, c->walls, fsh, true, false);
+    StepFn fn = pick_step(c->prec, c->flow, c->walls, Shape{}, true, false);
     StepArgs a = step_args(c, c->cur);
     a.dst = nullptr;
     a.step_out = nullptr;
@@ -643,7 +661,7 @@ int cmlb_read_fields(cmlb_ctx* c, int32_t sim, double* phi, double* cc, double* 
     a.ntiles = c->fntiles[sim];
     a.xcd_remap = 0;
     a.fields_out = c->d_stage;
-    hipLaunchKernelGGL(fn, dim3(c->fntiles[sim]), dim3(fsh.nw * 64), 0, c->stream, a);
+    hipLaunchKernelGGL(fn, dim3(c->fntiles[sim]), dim3(FIELD_NW * 64), 0, c->stream, a);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     double* outs[5] = {phi, cc, ux, uy, p};
@@ -739,20 +757,31 @@ int cmlb_synchronize(cmlb_ctx* c) {
     return sync_and_check(c);
 }
 
-int cmlb_set_tile_rows(cmlb_ctx* c, int32_t rows) {
+int cmlb_set_tile_shape(cmlb_ctx* c, int32_t width, int32_t rows) {
     if (!c) return CMLB_EINVAL;
-    if (rows != 0 && !rows_ok(c->prec, rows))
-        return fail(c, CMLB_EINVAL, "tile rows %d not supported", rows);
+    if ((width == 0) != (rows == 0))
+        return fail(c, CMLB_EINVAL, "tile width and rows must both be 0 or both set");
+    if (width != 0 && !shape_of(c->prec, width, rows, nullptr))
+        return fail(c, CMLB_EINVAL, "tile shape %dx%d not supported", width, rows);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->tile_w = width;
     c->tile_rows = rows;
     return build_tiles(c);
 }
 
-int cmlb_launch_options(const cmlb_ctx* c, int32_t* rows, int32_t cap) {
-    if (!c || (!rows && cap > 0)) return CMLB_EINVAL;
+int cmlb_set_tile_rows(cmlb_ctx* c, int32_t rows) {
+    if (!c) return CMLB_EINVAL;
+    return cmlb_set_tile_shape(c, rows ? 64 : 0, rows);
+}
+
+int cmlb_launch_options(const cmlb_ctx* c, int32_t* shapes, int32_t cap) {
+    if (!c || (!shapes && cap > 0)) return CMLB_EINVAL;
     const Shape* t = c->prec == CMLB_FP64 ? SHAPES_64 : SHAPES_32;
-    const int n = c->prec == CMLB_FP64 ? 2 : 4;
-    for (int i = 0; i < n && i < cap; ++i) rows[i] = t[i].rows;
+    const int n = c->prec == CMLB_FP64 ? N_SHAPES_64 : N_SHAPES_32;
+    for (int i = 0; i < n && 2 * i + 1 < cap; ++i) {
+        shapes[2 * i] = t[i].width;
+        shapes[2 * i + 1] = t[i].rows;
+    }
     return n;
 }
 

@@ -25,7 +25,7 @@
 
 namespace cmlb {
 
-constexpr int TX = 64;          // tile width: one wavefront across x
+constexpr int TX = 64;          // one wavefront spans 64 columns
 constexpr int WG = 256;         // threads per workgroup of the auxiliary kernels
 constexpr double NORMAL_EPS = 1e-12;
 
@@ -274,15 +274,19 @@ struct Occupancy {
 
 // NTS: population stores non-temporal (for lattices too large to stay in the
 // last-level cache between steps).
-template <class S, class T, int FLOW, bool WALLS, int NW, int NPT, bool FIELDS, bool NTS>
+// WX: wavefronts across x, so a tile is 64*WX columns by (NW/WX)*NPT rows;
+// wider tiles share fewer partly-used cache lines with their x neighbours.
+template <class S, class T, int FLOW, bool WALLS, int NW, int NPT, bool FIELDS, bool NTS, int WX>
 __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_step(const StepArgs a) {
+    static_assert(NW % WX == 0, "waves must tile the width");
     constexpr int CP = NTS ? CPOL_NT : 0;
     constexpr int NT = NW * 64;
     constexpr bool CPL = FLOW == FLOW_COUPLED;
     constexpr bool MOV = FLOW != FLOW_NONE;
-    constexpr int TY = NW * NPT;
-    constexpr int PW = TX + 4, PH = TY + 4;  // phi region (radius 2)
-    constexpr int QW = TX + 2, QH = TY + 2;  // c, P^, n region (radius 1)
+    constexpr int TW = TX * WX;
+    constexpr int TY = (NW / WX) * NPT;
+    constexpr int PW = TW + 4, PH = TY + 4;  // phi region (radius 2)
+    constexpr int QW = TW + 2, QH = TY + 2;  // c, P^, n region (radius 1)
     constexpr int RING = 4 * PW + 4 * TY;
     constexpr int SB = sizeof(S);
     __shared__ T phiL[PH * PW];
@@ -315,12 +319,14 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const int64_t step = *a.step_in;
     // tile, its radius-2 halo and their pull sources inside the grid: no
     // wrapping, no walls
-    const bool inner = x0 >= 3 && x0 + TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
+    const bool inner = x0 >= 3 && x0 + TW + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
     int so[9];
     pull_offsets(pb, nx, SB, so);
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    static_assert((WX & (WX - 1)) == 0, "WX must be a power of two");
+    const int wave = tid / TW;        // row block of this wavefront
+    const int lane = tid & (TW - 1);  // column within the tile
     const int gx = x0 + lane;
     const int lx = inner ? gx : wrap_coord(gx, nx);
 

@@ -22,7 +22,9 @@ def gpu_ctx(p_list, fls, precision="fp64", rows=None, graph=True):
     if isinstance(p_list, dict):
         p_list, fls = [p_list], [fls]
     ctx = cmlb.Context(p_list, precision)
-    if rows:
+    if isinstance(rows, tuple):
+        ctx.set_tile_shape(*rows)
+    elif rows:
         ctx.set_tile_rows(rows)
     ctx.set_use_graph(graph)
     for i, fl in enumerate(fls):

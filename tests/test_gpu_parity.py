@@ -164,17 +164,42 @@ def test_mass_drift_reported(gpu_lib, prec):
     assert db < (1e-5 if prec == "fp32" else 1e-2)
 
 
-def test_tile_shapes_bitwise_fp64(gpu_lib):
+SHAPES = {"fp64": [(64, 4), (64, 8), (128, 4)],
+          "fp32": [(64, 4), (64, 16), (64, 32), (128, 8), (128, 16)],
+          "fp16": [(64, 16), (128, 8), (128, 16)]}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_tile_shapes_bitwise(gpu_lib, prec):
+    """Every launch shape (64- and 128-column tiles, ragged in x and y: 150 x
+    45) gives the same populations bit for bit."""
     p, fl = W.random_fields(150, 45, seed=8, amp=1.0, sigma0=2e-3, beta=0.3, u_wall=2e-2,
                             M_phi=0.04)
     outs = []
-    for rows in (4, 8):
-        ctx = gpu_ctx(p, fl, "fp64", rows=rows)
+    for shape in SHAPES[prec]:
+        ctx = gpu_ctx(p, fl, prec, rows=shape)
+        assert shape in ctx.launch_options()
         ctx.step(60)
         outs.append(ctx.get_populations(0))
         ctx.close()
-    for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(a, b)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("flow", ["none", "prescribed"])
+def test_wide_tiles_two_lattice_bitwise(gpu_lib, flow):
+    """128-column tiles on the two-lattice paths (periodic and walls)."""
+    for bc in ("periodic", "walls"):
+        p, fl = W.random_fields(200, 37, seed=4, amp=1.0, flow=flow, bc_y=bc)
+        outs = []
+        for shape in ((64, 16), (128, 16)):
+            ctx = gpu_ctx(p, fl, "fp32", rows=shape)
+            ctx.step(40)
+            outs.append(ctx.get_populations(0))
+            ctx.close()
+        for a, b in zip(outs[0][:2], outs[1][:2]):
+            assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
