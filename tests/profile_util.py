@@ -41,3 +41,37 @@ def chat_exact(theta, t_star, nbins=None):
         h = np.pi / nbins
         f = np.sin(h) / h
     return 0.5 * (1.0 - np.exp(-t_star) * f * np.cos(theta))
+
+
+def taylor_deformation(phi, xc, yc, nray=720, level=0.5):
+    """Taylor deformation D = (L - B)/(L + B) of the phi = `level` contour
+    about (xc, yc): bilinear phi along `nray` rays (step 1/4), L and B the
+    longest and shortest diameters (sums of opposite radii)."""
+    ny, nx = phi.shape
+    th = np.linspace(0.0, 2 * np.pi, nray, endpoint=False)
+    rs = np.arange(0.0, min(nx, ny) / 2.0 - 2.0, 0.25)
+    X = xc + np.cos(th)[:, None] * rs[None, :]
+    Y = yc + np.sin(th)[:, None] * rs[None, :]
+    x0 = np.floor(X).astype(int)
+    y0 = np.floor(Y).astype(int)
+    fx, fy = X - x0, Y - y0
+    x0 %= nx
+    x1 = (x0 + 1) % nx
+    y0 = np.clip(y0, 0, ny - 1)
+    y1 = np.clip(y0 + 1, 0, ny - 1)
+    v = (phi[y0, x0] * (1 - fx) * (1 - fy) + phi[y0, x1] * fx * (1 - fy)
+         + phi[y1, x0] * (1 - fx) * fy + phi[y1, x1] * fx * fy)
+    r = np.empty(nray)
+    for i in range(nray):
+        k = int(np.argmax(v[i] < level))
+        a, b = v[i, k - 1], v[i, k]
+        r[i] = rs[k - 1] + (a - level) / (a - b) * (rs[k] - rs[k - 1])
+    d = r[: nray // 2] + r[nray // 2:]
+    L, B = d.max(), d.min()
+    return float((L - B) / (L + B))
+
+
+def stone_leal_D(Ca, beta, Pe, lam=1.0):
+    """Sec. 4.3 small-deformation prediction D = 3 Ca b_r/(4 + Ca b_r)."""
+    br = 1.25 * ((16 + 19 * lam) + 4 * beta * Pe / Ca) / (10 * (1 + lam) + 2 * beta * Pe / Ca)
+    return 3 * Ca * br / (4 + Ca * br)

@@ -114,3 +114,42 @@ def test_vortex_one_step_deep_in_the_run(oracle_mod, gpu_lib, prec, tol):
         print(prec, f"one-step max rel diff {d:.2e}")
         assert d <= tol, d
     ctx.close()
+
+
+# Sec. 4.3 table (clean and contaminated D x 1e-2 at Re = 0.1)
+PAPER_TABLE = {0.01: (1.60, 1.89), 0.02: (3.19, 3.72), 0.03: (4.77, 5.55),
+               0.04: (6.35, 7.36), 0.05: (7.93, 9.17)}
+
+
+def test_shear_drop_deformation_paper_scale(gpu_lib):
+    """Sec. 4.3 set-up: 768 x 256 channel, R = 32, Re = 0.1, Pe* = 0.5,
+    Ca = 0.01 ... 0.05, clean (beta = 0, no surfactant) and contaminated
+    (beta = 0.25, c0 = 0.3, D_s from Pe_s = 1); all ten drops in one launch,
+    FP32, 4e5 steps (gdot t = 3.9).  Checks what holds whatever the unstated
+    parameters: the clean D is steady and linear in Ca, and surfactant
+    raises D.  D against the paper's table and the Stone-Leal formula is
+    printed (context: the table's D/Ca is 1.5x Taylor's 3D value)."""
+    from profile_util import stone_leal_D, taylor_deformation
+    Cas = sorted(PAPER_TABLE)
+    cases = [W.shear_drop(nx=768, ny=256, R=32.0, Ca=ca, E=0.0, c0=0.0) for ca in Cas]
+    cases += [W.shear_drop(nx=768, ny=256, R=32.0, Ca=ca, E=0.25, c0=0.3, Pe_s=1.0)
+              for ca in Cas]
+    ctx = gpu_ctx([c[0] for c in cases], [c[1] for c in cases], "fp32")
+    D = {}
+    for steps in (300000, 100000):
+        ctx.step(steps)
+        D[steps] = [taylor_deformation(ctx.read_fields(i)["phi"], 384.0, 127.5)
+                    for i in range(len(cases))]
+    d3, d4 = D[300000], D[100000]
+    Pe = 0.1 * 0.1 / cases[5][0]["D_s"]
+    print("Ca   D_clean  D_cont  (x1e-2; table clean/cont; Stone-Leal clean/cont)")
+    for i, ca in enumerate(Cas):
+        print(f"{ca:.2f} {100 * d4[i]:7.3f} {100 * d4[5 + i]:7.3f}   {PAPER_TABLE[ca][0]:.2f}/"
+              f"{PAPER_TABLE[ca][1]:.2f}   {100 * stone_leal_D(ca, 0, Pe):.3f}/"
+              f"{100 * stone_leal_D(ca, 0.25, Pe):.3f}")
+    for i, ca in enumerate(Cas):
+        assert abs(d4[i] - d3[i]) < 0.02 * d4[i], (ca, d3[i], d4[i])  # clean: steady
+        assert d4[5 + i] > d4[i], ca                                  # surfactant raises D
+    slope = [d4[i] / ca for i, ca in enumerate(Cas)]
+    assert max(slope) / min(slope) < 1.05, slope                     # linear regime
+    ctx.close()

@@ -38,3 +38,27 @@ def test_oracle_profile_follows_closed_form(oracle_mod):
     err = np.abs(ch - chat_exact(th, D * steps / R ** 2, nbins=24)).max()
     # a plausible mistake (no diffusion, or twice the rate) is >= 0.09 off
     assert err < 1.5e-2, err
+
+
+def test_taylor_deformation_of_exact_ellipses():
+    """D of a diffuse ellipse (tanh profile across its boundary, W = 4) with
+    semi-axes a, b at several inclinations is (a - b)/(a + b) to 1e-3."""
+    from profile_util import taylor_deformation
+    ny, nx = 256, 768
+    x = np.arange(nx)[None, :] - 384.0
+    y = np.arange(ny)[:, None] - 127.5
+    for a, b, ang in ((40.0, 25.0, 0.5), (34.0, 30.0, 0.8), (32.0, 32.0, 0.0)):
+        xr = x * np.cos(ang) + y * np.sin(ang)
+        yr = -x * np.sin(ang) + y * np.cos(ang)
+        rr = np.sqrt((xr / a) ** 2 + (yr / b) ** 2)
+        phi = 0.5 + 0.5 * np.tanh(2 * (1 - rr) * np.sqrt(a * b) / 4.0)
+        assert abs(taylor_deformation(phi, 384.0, 127.5) - (a - b) / (a + b)) < 1e-3
+
+
+def test_stone_leal_reduces_to_its_clean_limit():
+    """beta = 0: b_r = 5(16 + 19 lam)/(40 (1 + lam)), independent of Pe."""
+    from profile_util import stone_leal_D
+    for Ca in (0.01, 0.05):
+        br = 5 * 35 / 80
+        assert abs(stone_leal_D(Ca, 0.0, 7.0) - 3 * Ca * br / (4 + Ca * br)) < 1e-15
+    assert stone_leal_D(0.01, 0.25, 1.0) > stone_leal_D(0.01, 0.0, 1.0)
