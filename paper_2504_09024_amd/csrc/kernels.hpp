@@ -109,7 +109,11 @@ struct Buf<_Float16> {
     template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
                                                  uint32_t rnd) {
-        const h16x2 h = __builtin_amdgcn_cvt_sr_f16_f32(h16x2{}, v, rnd, false);
+        // the conversion writes the low half of its destination and keeps
+        // the high half; passing v's own bits (dead after this) as that
+        // destination lets the compiler convert in place
+        const h16x2 h =
+            __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(h16x2, v), v, rnd, false);
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, so,
                                               CP);
     }
