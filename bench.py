@@ -233,6 +233,8 @@ def main():
                     help="cache policy of the population stores (default: library's choice)")
     ap.add_argument("--tile-group", type=int, default=-1,
                     help="column-group width of the tile order (default: library's)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default launch shape instead of timing the options")
     ap.add_argument("--no-forms", action="store_true", help="skip the other storage forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -291,6 +293,10 @@ def main():
         f"warmup {args.warmup}, steps {args.steps}")
     ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
                    not args.no_xcd_remap, args.tile_group, args.stores, args.tile_width)
+    tuned = None
+    if not args.no_autotune and not args.tile_rows and args.stores == "auto":
+        tuned = ctx.autotune(20)
+        log(f"[bench] autotuned launch: {tuned[0]}x{tuned[1]} tiles, {tuned[2]} stores")
     gpu_s, wall_s = timed_run(ctx, args.steps, args.warmup, torch)
     inv = ctx.inventory(0)
     ctx.close()
@@ -354,6 +360,7 @@ def main():
             "xcd_remap": not args.no_xcd_remap,
             "tile_group": args.tile_group if args.tile_group >= 0 else "default",
             "stores": args.stores,
+            "autotuned": (f"{tuned[0]}x{tuned[1]} tiles, {tuned[2]} stores" if tuned else None),
         },
         "roofline": {
             "bound": "hbm",

@@ -186,6 +186,18 @@ int cmlb_set_xcd_remap(cmlb_ctx* ctx, int32_t on);
  * it (bitwise). */
 int cmlb_set_store_policy(cmlb_ctx* ctx, int32_t policy);
 
+/* Autotuner: advance the context's own simulations by `steps` (1..100000)
+ * steps with every accepted tile shape under both store policies (default,
+ * non-temporal), time each trial with HIP events on the context's stream,
+ * and keep the fastest (written to *width, *rows, *policy when not NULL;
+ * policy as in cmlb_set_store_policy).  Every trial starts from a device
+ * copy of the current state, which is restored afterwards together with the
+ * step counter and fault flags: the simulations continue exactly as if no
+ * trial had run.  Needs one population buffer's worth of free device memory
+ * (CMLB_ENOMEM otherwise).  Synchronous.  On error the previous launch
+ * configuration and the state are restored. */
+int cmlb_autotune(cmlb_ctx* ctx, int32_t steps, int32_t* width, int32_t* rows, int32_t* policy);
+
 /* Order in which tiles are handed to workgroups: column groups of `group`
  * tiles of 64 columns (all tile rows of one group before the next), or 0
  * for plain row-major order (default).  Results do not depend on it. */

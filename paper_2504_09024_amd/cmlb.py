@@ -43,7 +43,7 @@ EXPORTS = (
     "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
     "cmlb_set_use_graph",
-    "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy",
+    "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy", "cmlb_autotune",
     "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
 )
 
@@ -86,6 +86,8 @@ def load(path: str = LIB_PATH):
     L.cmlb_set_xcd_remap.argtypes = [vp, ctypes.c_int32]
     L.cmlb_set_tile_order.argtypes = [vp, ctypes.c_int32]
     L.cmlb_set_store_policy.argtypes = [vp, ctypes.c_int32]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    L.cmlb_autotune.argtypes = [vp, ctypes.c_int32, ip, ip, ip]
     L.cmlb_step_count.argtypes = [vp]
     L.cmlb_step_count.restype = ctypes.c_int64
     L.cmlb_num_sims.argtypes = [vp]
@@ -252,6 +254,14 @@ class Context:
         if isinstance(policy, str):
             policy = {"auto": 0, "default": 1, "nt": 2}[policy]
         self._check(self.L.cmlb_set_store_policy(self.h, int(policy)), "cmlb_set_store_policy")
+
+    def autotune(self, steps=20):
+        """Time every launch option on these simulations (state restored);
+        keeps and returns the fastest as (width, rows, store policy)."""
+        w, r, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.L.cmlb_autotune(self.h, int(steps), ctypes.byref(w), ctypes.byref(r),
+                                         ctypes.byref(p)), "cmlb_autotune")
+        return w.value, r.value, {1: "default", 2: "nt"}[p.value]
 
     def set_tile_order(self, group):
         self._check(self.L.cmlb_set_tile_order(self.h, int(group)), "cmlb_set_tile_order")

@@ -799,6 +799,103 @@ int cmlb_set_xcd_remap(cmlb_ctx* c, int32_t on) {
     return CMLB_OK;
 }
 
+// Autotuner: every (tile shape, store policy) pair advances the context's
+// own simulations by `steps` direct launches, timed with HIP events, each
+// trial starting from the same saved state; the fastest pair is kept and the
+// state restored, so the run continues bitwise as if no trial had happened.
+int cmlb_autotune(cmlb_ctx* c, int32_t steps, int32_t* width, int32_t* rows, int32_t* policy) {
+    if (!c || steps < 1 || steps > 100000) return CMLB_EINVAL;
+    for (int s = 0; s < c->n_sims; ++s)
+        if (!c->inited[s]) return fail(c, CMLB_ESTATE, "simulation %d not initialised", s);
+    if (c->fault_seen) return fail(c, CMLB_ERANGE, "a fault flag was raised earlier");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int cur0 = c->cur;
+    const int64_t step0 = c->step;
+    const int w0 = c->tile_w, r0 = c->tile_rows, p0 = c->store_policy, g0 = c->use_graph;
+    int64_t dstep[2];
+    std::vector<int32_t> fault(c->n_sims);
+    HIP_TRY(c, hipMemcpy(dstep, c->d_step, sizeof(dstep), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(fault.data(), c->d_fault, sizeof(int32_t) * c->n_sims,
+                         hipMemcpyDeviceToHost));
+    void* save = nullptr;
+    if (hipMalloc(&save, c->pop_bytes) != hipSuccess)
+        return fail(c, CMLB_ENOMEM, "no device memory for the autotuner's state copy");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = CMLB_OK;
+    auto restore = [&]() -> int {
+        c->cur = cur0;
+        c->step = step0;
+        HIP_TRY(c, hipMemcpyAsync(c->pop[cur0], save, c->pop_bytes, hipMemcpyDeviceToDevice,
+                                  c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_step, dstep, sizeof(dstep), hipMemcpyHostToDevice,
+                                  c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->d_fault, fault.data(), sizeof(int32_t) * c->n_sims,
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return CMLB_OK;
+    };
+    const Shape* t = c->prec == CMLB_FP64 ? SHAPES_64 : SHAPES_32;
+    const int n = c->prec == CMLB_FP64 ? N_SHAPES_64 : N_SHAPES_32;
+    float best = 0.f;
+    int bw = 0, br = 0, bp = 0;
+    do {
+        if (hipMemcpyAsync(save, c->pop[cur0], c->pop_bytes, hipMemcpyDeviceToDevice,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = fail(c, CMLB_EDEVICE, "autotuner set-up failed");
+            break;
+        }
+        c->use_graph = 0;
+        for (int i = 0; i < n && rc == CMLB_OK; ++i)
+            for (int pol = 1; pol <= 2 && rc == CMLB_OK; ++pol) {
+                c->tile_w = t[i].width;
+                c->tile_rows = t[i].rows;
+                c->store_policy = pol;
+                if ((rc = build_tiles(c)) != CMLB_OK) break;
+                if ((rc = cmlb_step(c, 2)) != CMLB_OK) break;
+                if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = CMLB_EDEVICE; break; }
+                if ((rc = cmlb_step(c, steps)) != CMLB_OK) break;
+                float ms = 0.f;
+                if (hipEventRecord(e1, c->stream) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = fail(c, CMLB_EDEVICE, "autotuner timing failed");
+                    break;
+                }
+                if (bw == 0 || ms < best) {
+                    best = ms;
+                    bw = t[i].width;
+                    br = t[i].rows;
+                    bp = pol;
+                }
+                if ((rc = restore()) != CMLB_OK) break;
+            }
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != CMLB_OK) {
+        (void)restore();
+        (void)hipFree(save);
+        c->tile_w = w0;
+        c->tile_rows = r0;
+        c->store_policy = p0;
+        c->use_graph = g0;
+        (void)build_tiles(c);
+        return rc;
+    }
+    (void)hipFree(save);
+    c->tile_w = bw;
+    c->tile_rows = br;
+    c->store_policy = bp;
+    c->use_graph = g0;
+    if ((rc = build_tiles(c)) != CMLB_OK) return rc;
+    if (width) *width = bw;
+    if (rows) *rows = br;
+    if (policy) *policy = bp;
+    return CMLB_OK;
+}
+
 int cmlb_set_store_policy(cmlb_ctx* c, int32_t policy) {
     if (!c || policy < 0 || policy > 2) return CMLB_EINVAL;
     HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -203,6 +203,27 @@ def test_wide_tiles_two_lattice_bitwise(gpu_lib, flow):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_autotune_leaves_the_run_unchanged(gpu_lib, prec):
+    """The autotuner's trials leave no trace: 10 steps, autotune, 20 steps
+    equals 30 plain steps bit for bit, and the step counter is kept."""
+    p, fl = W.random_fields(150, 45, seed=8, amp=1.0, sigma0=2e-3, beta=0.3, u_wall=2e-2,
+                            M_phi=0.04)
+    a = gpu_ctx(p, fl, prec)
+    a.step(10)
+    w, r, pol = a.autotune(5)
+    assert (w, r) in a.launch_options() and pol in ("default", "nt")
+    assert a.step_count == 10
+    a.step(20)
+    b = gpu_ctx(p, fl, prec)
+    b.step(30)
+    for x, y in zip(a.get_populations(0), b.get_populations(0)):
+        assert np.array_equal(x, y)
+    assert a.fault_flags(0) == 0
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_store_policy_bitwise(gpu_lib, prec):
     """Default and non-temporal population stores give identical results."""
     p, fl = W.random_fields(150, 45, seed=8, amp=1.0, sigma0=2e-3, beta=0.3, u_wall=2e-2,
