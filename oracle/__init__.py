@@ -20,6 +20,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "cmlb_oracle.c")
+SRC3 = os.path.join(HERE, "cmlb3_oracle.c")
+SOURCES = (SRC, SRC3, os.path.join(HERE, "cmlb_oracle.h"), os.path.join(HERE, "cmlb3_oracle.h"))
 
 FLOW_NONE, FLOW_PRESCRIBED, FLOW_COUPLED = 0, 1, 2
 DIAG_NAMES = (
@@ -32,7 +34,7 @@ def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (OpenMP over rows; results do not depend on
     the thread count because no value is reduced across threads)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE",
-           "-Wall", SRC, "-o", LIB_PATH + ".tmp", "-lm"]
+           "-Wall", SRC, SRC3, "-o", LIB_PATH + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)
@@ -60,7 +62,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB_PATH) or any(
+                os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in SOURCES):
             build()
         L = ctypes.CDLL(LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -83,6 +86,7 @@ def lib():
         L.o_fields.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.o_node_diag.argtypes = [pp, ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_int,
                                   ctypes.c_int, dp]
+        _declare3(L)
         _lib = L
     return _lib
 
@@ -250,3 +254,161 @@ class OracleSim:
                           _ptr(self.uy_shape), _ptr(self.f), _ptr(self.h), _ptr(self.g), x, y,
                           _ptr(out))
         return dict(zip(DIAG_NAMES, out))
+
+
+# ---- three-dimensional (D3Q27) form ----------------------------------------
+
+class OParams3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("walls", ctypes.c_int32), ("flow", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("W", ctypes.c_double), ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double),
+        ("M_phi", ctypes.c_double), ("D_s", ctypes.c_double),
+        ("rho_a", ctypes.c_double), ("rho_b", ctypes.c_double), ("nu_a", ctypes.c_double),
+        ("nu_b", ctypes.c_double), ("omega_zeta", ctypes.c_double),
+        ("sigma0", ctypes.c_double), ("beta", ctypes.c_double), ("c_max", ctypes.c_double),
+        ("u_wall", ctypes.c_double), ("F_ext_x", ctypes.c_double), ("F_ext_y", ctypes.c_double),
+        ("F_ext_z", ctypes.c_double), ("vel_period_T", ctypes.c_double),
+    ]
+
+
+def _declare3(L):
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    pp = ctypes.POINTER(OParams3)
+    L.o3_directions.argtypes = [ip, ip, ip]
+    L.o3_weights.argtypes = [dp]
+    L.o3_central_moments.argtypes = [dp, dp, dp]
+    L.o3_populations_from_central.argtypes = [dp, dp, dp]
+    L.o3_populations_from_central_solve.argtypes = [dp, dp, dp]
+    L.o3_collide_scalar.argtypes = [dp, dp, ctypes.c_double, dp, ctypes.c_double, dp]
+    L.o3_collide_flow.argtypes = [dp, dp, ctypes.c_double, ctypes.c_double, dp, dp,
+                                  ctypes.c_double, ctypes.c_double, dp]
+    L.o3_check_params.argtypes = [pp]
+    L.o3_init.argtypes = [pp] + [dp] * 9
+    L.o3_step.argtypes = [pp, ctypes.c_int64] + [dp] * 7
+    L.o3_run.argtypes = [pp, ctypes.c_int64, ctypes.c_int64] + [dp] * 4
+    L.o3_fields.argtypes = [pp, ctypes.c_int64] + [dp] * 10
+
+
+PARAM_KEYS3 = [f[0] for f in OParams3._fields_ if f[0] != "pad_"]
+
+
+def make_params3(**kw) -> OParams3:
+    """Parameter block of the 3D oracle (keys as the library's; ``bc_y`` and
+    ``flow`` may be strings)."""
+    p = OParams3()
+    d = dict(kw)
+    bc = d.pop("bc_y", None)
+    if bc is not None:
+        d["walls"] = 1 if bc in ("walls", "moving_walls", 1) else 0
+    fl = d.pop("flow", None)
+    if fl is not None:
+        d["flow"] = {"none": 0, "prescribed": 1, "coupled": 2}.get(fl, fl)
+    for k, v in d.items():
+        if k in PARAM_KEYS3:
+            setattr(p, k, v)
+    return p
+
+
+def directions3():
+    ex, ey, ez = ((ctypes.c_int * 27)() for _ in range(3))
+    lib().o3_directions(ex, ey, ez)
+    return np.array(list(ex)), np.array(list(ey)), np.array(list(ez))
+
+
+def weights3():
+    out = np.zeros(27)
+    lib().o3_weights(_ptr(out))
+    return out
+
+
+def central_moments3(q, u):
+    q, u = _vec(q), _vec(u)
+    out = np.zeros(27)
+    lib().o3_central_moments(_ptr(q), _ptr(u), _ptr(out))
+    return out
+
+
+def populations_from_central3(kappa, u, solve=False):
+    k, u = _vec(kappa), _vec(u)
+    out = np.zeros(27)
+    if solve:
+        if lib().o3_populations_from_central_solve(_ptr(k), _ptr(u), _ptr(out)) != 0:
+            raise ValueError("singular moment system")
+    else:
+        lib().o3_populations_from_central(_ptr(k), _ptr(u), _ptr(out))
+    return out
+
+
+def collide_scalar3(q, u, s, j, omega1):
+    q, u, j = _vec(q), _vec(u), _vec(j)
+    out = np.zeros(27)
+    lib().o3_collide_scalar(_ptr(q), _ptr(u), s, _ptr(j), omega1, _ptr(out))
+    return out
+
+
+def collide_flow3(g, u, P, rho, fp, ft, omega_zeta, omega_nu):
+    g, u, fp, ft = _vec(g), _vec(u), _vec(fp), _vec(ft)
+    out = np.zeros(27)
+    lib().o3_collide_flow(_ptr(g), _ptr(u), P, rho, _ptr(fp), _ptr(ft), omega_zeta, omega_nu,
+                          _ptr(out))
+    return out
+
+
+class OracleSim3:
+    """One 3D simulation as FP64 numpy population arrays [27][nz][ny][nx]."""
+
+    def __init__(self, params: OParams3, phi, c, ux=None, uy=None, uz=None, P=None):
+        self.p = params
+        rc = lib().o3_check_params(ctypes.byref(params))
+        if rc != 0:
+            raise ValueError(f"invalid oracle parameters (code {rc})")
+        sh = (params.nz, params.ny, params.nx)
+        self.f = np.zeros((27,) + sh)
+        self.h = np.zeros((27,) + sh)
+        self.coupled = params.flow == FLOW_COUPLED
+        self.g = np.zeros((27,) + sh) if self.coupled else None
+        arrs = [None if a is None else _vec(a).reshape(sh) for a in (phi, c, ux, uy, uz, P)]
+        if params.flow == FLOW_PRESCRIBED:
+            self.ushape = np.ascontiguousarray(np.stack(
+                [a if a is not None else np.zeros(sh) for a in arrs[2:5]]))
+        else:
+            self.ushape = None
+        rc = lib().o3_init(ctypes.byref(params), *[_ptr(a) for a in arrs], _ptr(self.f),
+                           _ptr(self.h), _ptr(self.g))
+        if rc != 0:
+            raise RuntimeError(f"oracle init failed ({rc})")
+        self.t = 0
+
+    @classmethod
+    def from_populations(cls, params, f, h, g=None, t=0, ushape=None):
+        self = cls.__new__(cls)
+        self.p = params
+        self.f = np.ascontiguousarray(f, dtype=np.float64).copy()
+        self.h = np.ascontiguousarray(h, dtype=np.float64).copy()
+        self.coupled = params.flow == FLOW_COUPLED
+        self.g = None if g is None else np.ascontiguousarray(g, dtype=np.float64).copy()
+        self.ushape = None if ushape is None else _vec(ushape)
+        self.t = t
+        return self
+
+    def run(self, nsteps: int) -> int:
+        fault = lib().o3_run(ctypes.byref(self.p), self.t, nsteps, _ptr(self.ushape),
+                             _ptr(self.f), _ptr(self.h), _ptr(self.g))
+        self.t += nsteps
+        return fault
+
+    def fields(self):
+        sh = (self.p.nz, self.p.ny, self.p.nx)
+        out = {k: np.zeros(sh) for k in ("phi", "c", "ux", "uy", "uz", "P")}
+        fault = lib().o3_fields(ctypes.byref(self.p), self.t, _ptr(self.ushape), _ptr(self.f),
+                                _ptr(self.h), _ptr(self.g), _ptr(out["phi"]), _ptr(out["c"]),
+                                _ptr(out["ux"]), _ptr(out["uy"]), _ptr(out["uz"]),
+                                _ptr(out["P"]))
+        out["fault"] = fault
+        return out
+
+    def inventory(self):
+        import math
+        return math.fsum(self.f.ravel()), math.fsum(self.h.ravel())

@@ -1,0 +1,211 @@
+"""CPU pins of the 3D (D3Q27) oracle.
+
+The paper states its schemes in 2D only; the 3D oracle follows them axis by
+axis.  It is pinned by: the textbook D3Q27 weights; the axis-wise inverse
+against a dense 27x27 solve; single-node properties (fixed points,
+conservation, the momentum source); and reduction to the independently
+pinned 2D oracle -- a field uniform along z, and one uniform along y (the x-z
+plane), must evolve exactly like the 2D scheme (the flow lattice when
+omega_zeta = omega_nu, where the 3D trace/deviatoric split and the 2D
+sum/difference split coincide)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_09024_amd import workloads as W
+
+CS2 = 1.0 / 3.0
+
+
+def test_weights_are_the_d3q27_products(oracle_mod):
+    w = oracle_mod.weights3()
+    ex, ey, ez = oracle_mod.directions3()
+    w1 = {0: 2.0 / 3.0, 1: 1.0 / 6.0, -1: 1.0 / 6.0}
+    expect = np.array([w1[a] * w1[b] * w1[c] for a, b, c in zip(ex, ey, ez)])
+    assert np.allclose(w, expect, rtol=0, atol=5e-16)
+    assert sorted(set(np.round(w * 216).astype(int))) == [1, 4, 16, 64]
+    assert len(set(zip(ex, ey, ez))) == 27
+
+
+def test_axis_inverse_matches_dense_solve(oracle_mod):
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        k = rng.normal(size=27)
+        u = rng.uniform(-0.3, 0.3, 3)
+        a = oracle_mod.populations_from_central3(k, u)
+        b = oracle_mod.populations_from_central3(k, u, solve=True)
+        assert np.abs(a - b).max() < 1e-13 * max(1.0, np.abs(b).max())
+        # and it inverts the definition sums
+        assert np.allclose(oracle_mod.central_moments3(a, u), k, rtol=0, atol=1e-13)
+
+
+def test_scalar_collision_conserves_and_relaxes(oracle_mod):
+    rng = np.random.default_rng(3)
+    q = rng.uniform(0.0, 0.1, 27)
+    u = rng.uniform(-0.05, 0.05, 3)
+    j = rng.uniform(-0.01, 0.01, 3)
+    om = 1.3
+    s = q.sum()
+    qt = oracle_mod.collide_scalar3(q, u, s, j, om)
+    assert abs(qt.sum() - s) < 1e-15
+    k0 = oracle_mod.central_moments3(q, u)
+    k1 = oracle_mod.central_moments3(qt, u)
+    for m, d in ((1, 0), (3, 1), (9, 2)):
+        assert abs(k1[m] - ((1 - om) * k0[m] + om * j[d])) < 1e-15
+    # higher moments at the product equilibrium s prod c(a_i)
+    c = (1.0, 0.0, CS2)
+    for m in range(27):
+        if (m % 3) + ((m // 3) % 3) + (m // 9) >= 2:
+            assert abs(k1[m] - s * c[m % 3] * c[(m // 3) % 3] * c[m // 9]) < 1e-15
+    # the rest state with J = 0 and u = 0 is a fixed point
+    w = oracle_mod.weights3()
+    assert np.abs(oracle_mod.collide_scalar3(0.7 * w, np.zeros(3), 0.7, np.zeros(3), om)
+                  - 0.7 * w).max() < 1e-15
+
+
+def test_flow_collision_momentum_source(oracle_mod):
+    """Sum e (g~ - g) = cs2 F_t and sum (g~ - g) = Gamma = F_p.u when u and P
+    are the velocity and pressure of the node (u = (sum e g + cs2 F_t/2)/
+    (cs2 rho), P = sum g + Gamma/2)."""
+    rng = np.random.default_rng(11)
+    ex, ey, ez = oracle_mod.directions3()
+    E = np.stack([ex, ey, ez]).astype(float)
+    w = oracle_mod.weights3()
+    g = w * CS2 + rng.normal(scale=1e-3, size=27) * w
+    rho = 1.1
+    ft = rng.normal(scale=1e-3, size=3)
+    fp = rng.normal(scale=1e-3, size=3)
+    u = (E @ g + 0.5 * CS2 * ft) / (CS2 * rho)
+    gam = fp @ u
+    P = g.sum() + 0.5 * gam
+    gt = oracle_mod.collide_flow3(g, u, P, rho, fp, ft, 0.9, 1.2)
+    assert np.abs(E @ (gt - g) - CS2 * ft).max() < 1e-15
+    assert abs((gt - g).sum() - gam) < 1e-15
+
+
+def _marginal_over_z(oracle_mod, q3):
+    """2D populations from 3D ones: for each 2D direction (ex, ey), the sum
+    of the three 3D directions (ex, ey, ez), ez in {-1, 0, 1}."""
+    ex2, ey2 = oracle_mod.directions()
+    ex, ey, ez = oracle_mod.directions3()
+    return np.stack([q3[(ex == a) & (ey == b)].sum(axis=0) for a, b in zip(ex2, ey2)])
+
+
+def _params3(p2, nz, **over):
+    d = dict(p2)
+    d["nz"] = nz
+    d.update(over)
+    return d
+
+
+CASES_2D = {
+    "none": lambda: W.random_fields(24, 20, seed=2, amp=1.0, flow="none", bc_y="periodic"),
+    "prescribed": lambda: W.random_fields(24, 20, seed=4, amp=1.0, flow="prescribed",
+                                          bc_y="periodic"),
+    "coupled_walls": lambda: W.random_fields(24, 20, seed=5, amp=1.0, sigma0=2e-3, beta=0.3,
+                                             u_wall=2e-2, M_phi=0.04, D_s=0.02,
+                                             omega_zeta=1.0 / (3 * 0.1 + 0.5)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES_2D))
+def test_z_uniform_field_reduces_to_the_2d_oracle(oracle_mod, name):
+    p2, fl = CASES_2D[name]()
+    steps = 30
+    o2 = oracle_mod.OracleSim(oracle_mod.make_params(**p2), fl["phi"], fl["c"], fl.get("ux"),
+                              fl.get("uy"), fl.get("P"))
+    assert o2.run(steps) == 0
+    r2 = o2.fields()
+    sh = (1,) + fl["phi"].shape
+    p3 = oracle_mod.make_params3(**_params3(p2, 1))
+    z = lambda a: None if a is None else a.reshape(sh)
+    o3 = oracle_mod.OracleSim3(p3, z(fl["phi"]), z(fl["c"]), z(fl.get("ux")), z(fl.get("uy")),
+                               None, z(fl.get("P")))
+    assert o3.run(steps) == 0
+    r3 = o3.fields()
+    # phi, c to 1e-13 relative; u and P are formed from O(cs2) populations,
+    # so their rounding floor is ~1e-16 absolute (checked at 1e-14)
+    for k in ("phi", "c", "ux", "uy", "P"):
+        scale = max(np.abs(r2[k]).max(), 1e-30) if k in ("phi", "c") else 1.0
+        assert np.abs(r3[k][0] - r2[k]).max() <= 1e-13 * scale + 1e-18, k
+    assert np.abs(r3["uz"]).max() < 1e-15
+    # populations: the 2D ones are the marginals of the 3D ones over e_z
+    assert np.abs(_marginal_over_z(oracle_mod, o3.f[:, 0]) - o2.f).max() < 1e-14
+    assert np.abs(_marginal_over_z(oracle_mod, o3.h[:, 0]) - o2.h).max() < 1e-14
+
+
+def test_y_uniform_field_reduces_to_the_2d_oracle_in_the_xz_plane(oracle_mod):
+    """x-z plane: the 2D (x, y) run mapped to 3D (x, z), uniform along a
+    periodic y; exercises every z-specific term of the 3D step."""
+    p2, fl = W.random_fields(20, 16, seed=9, amp=1.0, sigma0=2e-3, beta=0.3, M_phi=0.04,
+                             D_s=0.02, bc_y="periodic", F_ext_x=1e-5, F_ext_y=-2e-5,
+                             omega_zeta=1.0 / (3 * 0.1 + 0.5))
+    steps = 20
+    o2 = oracle_mod.OracleSim(oracle_mod.make_params(**p2), fl["phi"], fl["c"], fl["ux"],
+                              fl["uy"], fl["P"])
+    assert o2.run(steps) == 0
+    r2 = o2.fields()
+    nz, nx = fl["phi"].shape
+    ny = 4
+    d3 = dict(p2, nz=nz, ny=ny, F_ext_z=p2["F_ext_y"], F_ext_y=0.0)
+    p3 = oracle_mod.make_params3(**d3)
+    b = lambda a: np.ascontiguousarray(np.broadcast_to(a[:, None, :], (nz, ny, nx)))
+    o3 = oracle_mod.OracleSim3(p3, b(fl["phi"]), b(fl["c"]), b(fl["ux"]), None, b(fl["uy"]),
+                               b(fl["P"]))
+    assert o3.run(steps) == 0
+    r3 = o3.fields()
+    for k2, k3 in (("phi", "phi"), ("c", "c"), ("ux", "ux"), ("uy", "uz"), ("P", "P")):
+        scale = max(np.abs(r2[k2]).max(), 1e-30) if k2 in ("phi", "c") else 1.0
+        for y in range(ny):
+            assert np.abs(r3[k3][:, y, :] - r2[k2]).max() <= 1e-13 * scale + 1e-18, k2
+    assert np.abs(r3["uy"]).max() < 1e-15
+
+
+def test_conservation_3d_walls(oracle_mod):
+    """Sum phi and sum c are conserved to rounding with moving walls."""
+    rng = np.random.default_rng(1)
+    nx, ny, nz = 16, 12, 10
+    x = np.arange(nx)[None, None, :] - 7.6
+    y = np.arange(ny)[None, :, None] + 0.5 - 6.2
+    z = np.arange(nz)[:, None, None] - 4.9
+    r = np.sqrt(x * x + y * y + z * z)
+    phi = 0.5 + 0.5 * np.tanh(2 * (4.5 - r) / 4.0)
+    c = 0.3 / np.cosh(2 * (4.5 - r) / 4.0) ** 2
+    ux = 1e-2 * (2 * (np.arange(ny)[None, :, None] + 0.5) / ny - 1) * np.ones((nz, ny, nx))
+    p = oracle_mod.make_params3(nx=nx, ny=ny, nz=nz, walls=1, flow="coupled", W=4.0,
+                                phi_a=1.0, phi_b=0.0, M_phi=0.04, D_s=0.02, rho_a=1.0,
+                                rho_b=1.0, nu_a=0.1, nu_b=0.1, omega_zeta=1.0, sigma0=2e-3,
+                                beta=0.3, c_max=1.0, u_wall=1e-2)
+    o = oracle_mod.OracleSim3(p, phi, c, ux, None, None, None)
+    s0 = o.inventory()
+    assert o.run(40) == 0
+    s1 = o.inventory()
+    assert abs(s1[0] - s0[0]) / s0[0] < 1e-13
+    assert abs(s1[1] - s0[1]) / s0[1] < 1e-13
+
+
+def test_shear_wave_3d_decays_at_the_shear_viscosity(oracle_mod):
+    """u_x = A sin(2 pi z/L) in a uniform fluid decays as exp(-nu k^2 t)
+    whatever the bulk rate: run with omega_zeta far from omega_nu, where a
+    trace/deviatoric mix-up would change the rate."""
+    nx, ny, nz = 4, 4, 32
+    nu = 0.1
+    A = 1e-3
+    z = np.arange(nz)[:, None, None] * np.ones((nz, ny, nx))
+    ux = A * np.sin(2 * np.pi * z / nz)
+    p = oracle_mod.make_params3(nx=nx, ny=ny, nz=nz, walls=0, flow="coupled", W=4.0,
+                                phi_a=1.0, phi_b=0.0, M_phi=0.1, D_s=0.1, rho_a=1.0, rho_b=1.0,
+                                nu_a=nu, nu_b=nu, omega_zeta=1.7, sigma0=0.0, beta=0.0,
+                                c_max=1.0)
+    o = oracle_mod.OracleSim3(p, np.ones((nz, ny, nx)), np.zeros((nz, ny, nx)), ux, None, None,
+                              None)
+    steps = 200
+    assert o.run(steps) == 0
+    f = o.fields()
+    amp = 2 * (f["ux"] * np.sin(2 * np.pi * z / nz)).mean()
+    k = 2 * np.pi / nz
+    measured = -math.log(amp / A) / steps
+    assert abs(measured / (nu * k * k) - 1) < 5e-3, measured / (nu * k * k)
+    # no transverse flow beyond the O(A^2) compressibility level
+    assert np.abs(f["uz"]).max() < 1e-8 and np.abs(f["uy"]).max() < 1e-8
