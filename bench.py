@@ -31,7 +31,8 @@ METRIC = "coupled MLUPS and % HBM roofline, FP32/FP16-storage/batched vs FP64 GP
 HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 ARITH = {"fp64": "f64", "fp32": "f32", "fp16": "f32"}
-KERNEL_SOURCES = ("paper_2504_09024_amd/csrc/kernels.hpp", "paper_2504_09024_amd/csrc/lattice.hpp")
+KERNEL_SOURCES = ("paper_2504_09024_amd/csrc/kernels.hpp", "paper_2504_09024_amd/csrc/lattice.hpp",
+                  "paper_2504_09024_amd/csrc/device_common.hpp")
 
 
 def log(*a):

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcmlb.so")
 SOURCES = [os.path.join(HERE, "csrc", "cmlb.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "lattice.hpp")] + [
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "lattice.hpp", "device_common.hpp")] + [
     os.path.join(ROOT, "include", "cmlb.h")]
 ARCH = os.environ.get("CMLB_OFFLOAD_ARCH", "gfx950")
 

@@ -45,94 +45,6 @@ struct StepArgs {
     double* fields_out;     // fields mode: [5][ny][nx] (phi, c, ux, uy, P)
 };
 
-template <class S>
-struct Store {
-    static constexpr bool scaled = false;
-};
-template <>
-struct Store<_Float16> {
-    static constexpr bool scaled = true;
-};
-
-// ---------------------------------------------------------------------------
-// Storage access through buffer descriptors: one descriptor per lattice, the
-// node offset in a VGPR and the direction plane in the SGPR offset, so the 27
-// loads and stores of a node share one address computation.  Out-of-range
-// buffer accesses return 0 / are dropped by the hardware.
-// ---------------------------------------------------------------------------
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, 0x00020000);
-}
-
-// Stores take a cache policy CP: 0 = default, CPOL_NT = non-temporal
-// (streamed past the caches rather than kept in them).
-constexpr int CPOL_NT = 2;
-
-template <class S>
-struct Buf;
-template <>
-struct Buf<double> {
-    static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
-    }
-    template <int CP>
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, double v,
-                                                 uint32_t) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, vo, so, CP);
-    }
-};
-template <>
-struct Buf<float> {
-    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
-    }
-    template <int CP>
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
-                                                 uint32_t) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, CP);
-    }
-};
-// binary16 storage: loads widen exactly; stores round stochastically with
-// gfx950's v_cvt_sr_f16_f32 (the top 13 bits of the random word decide the
-// rounding direction; exactly representable values are kept).  Stochastic
-// rounding keeps the per-step storage errors independent and unbiased, where
-// round-to-nearest would repeat the same error every step at a quasi-steady
-// node.
-template <>
-struct Buf<_Float16> {
-    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
-        return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)));
-    }
-    template <int CP>
-    static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
-                                                 uint32_t rnd) {
-        // the conversion writes the low half of its destination and keeps
-        // the high half; passing v's own bits (dead after this) as that
-        // destination lets the compiler convert in place
-        const h16x2 h =
-            __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(h16x2, v), v, rnd, false);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, so,
-                                              CP);
-    }
-};
-
-// Counter-based random words for the stochastic rounding: the MurmurHash3
-// 32-bit finaliser of (node, step) gives a per-node seed; the word for store
-// k of the node is seed + k * 0x9E3779B9 (a Weyl sequence: one add each, and
-// its top bits -- the ones the conversion uses -- are equidistributed).
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-    h ^= h >> 16;
-    h *= 0x85ebca6bu;
-    h ^= h >> 13;
-    h *= 0xc2b2ae35u;
-    h ^= h >> 16;
-    return h;
-}
-__device__ __forceinline__ constexpr uint32_t weyl(int k) { return (uint32_t)k * 0x9E3779B9u; }
-
 // Moments of stored scalar-lattice values in storage units.  No FP
 // contraction: a node's zeroth moment must carry the same bits in every code
 // path that computes it (tile interior and neighbouring tiles' halos).
@@ -256,14 +168,6 @@ __device__ __forceinline__ const PhysConsts<float>& consts<float>(const SimDev* 
     return sd->kf;
 }
 
-// Fast approximate operations for the FP32 path (1-2 ulp), exact IEEE ones
-// for FP64 (the FP64 path is checked against the oracle at 1e-12).
-__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-__device__ __forceinline__ float log_(float x) { return __logf(x); }
-__device__ __forceinline__ double log_(double x) { return log(x); }
 
 // ---------------------------------------------------------------------------
 // The fused step kernel.  FIELDS = true evaluates phases 1-3 up to the

@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_common.hpp"
+
 namespace cmlb {
 
 enum { FLOW_NONE = 0, FLOW_PRESCRIBED = 1, FLOW_COUPLED = 2 };
@@ -338,21 +340,6 @@ __device__ __forceinline__ void lds_grad(const T* L, int idx, T& gx, T& gy) {
     const T se = L[idx - P + 1], sw = L[idx - P - 1];
     gx = (e - w) * K<T>::third + ((ne - nw) + (se - sw)) * K<T>::twelfth;
     gy = (n - s) * K<T>::third + ((ne + nw) - (se + sw)) * K<T>::twelfth;
-}
-
-// Coordinate folding: periodic wrap, or mirror about the wall planes
-// y = -1/2 and y = n - 1/2 (ghost row -1-k carries row k).
-__device__ __forceinline__ int wrap_coord(int v, int n) {
-    if (v >= 0 && v < n) return v;
-    int m = v % n;
-    return m < 0 ? m + n : m;
-}
-__device__ __forceinline__ int mirror_coord(int v, int n) {
-    if (v >= 0 && v < n) return v;
-    const int p = 2 * n;
-    int m = v % p;
-    if (m < 0) m += p;
-    return m < n ? m : p - 1 - m;
 }
 
 }  // namespace cmlb
