@@ -15,9 +15,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcmlb.so")
-SOURCES = [os.path.join(HERE, "csrc", "cmlb.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("kernels.hpp", "lattice.hpp", "device_common.hpp")] + [
-    os.path.join(ROOT, "include", "cmlb.h")]
+SOURCES = [os.path.join(HERE, "csrc", "cmlb.hip"), os.path.join(HERE, "csrc", "cmlb3.hip")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f)
+                  for f in ("kernels.hpp", "lattice.hpp", "device_common.hpp", "kernels3.hpp")] + [
+    os.path.join(ROOT, "include", f) for f in ("cmlb.h", "cmlb3.h")]
 ARCH = os.environ.get("CMLB_OFFLOAD_ARCH", "gfx950")
 
 

@@ -47,6 +47,27 @@ EXPORTS = (
     "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
 )
 
+EXPORTS3 = (
+    "cmlb3_create", "cmlb3_init_fields", "cmlb3_step", "cmlb3_read_fields", "cmlb3_inventory",
+    "cmlb3_get_populations", "cmlb3_set_populations", "cmlb3_fault_flags", "cmlb3_synchronize",
+    "cmlb3_set_use_graph", "cmlb3_step_count", "cmlb3_last_error", "cmlb3_destroy",
+)
+
+
+class SimParams3(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc_y", ctypes.c_int32), ("flow", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("W", ctypes.c_double), ("phi_a", ctypes.c_double), ("phi_b", ctypes.c_double),
+        ("M_phi", ctypes.c_double), ("D_s", ctypes.c_double),
+        ("rho_a", ctypes.c_double), ("rho_b", ctypes.c_double), ("nu_a", ctypes.c_double),
+        ("nu_b", ctypes.c_double), ("omega_zeta", ctypes.c_double),
+        ("sigma0", ctypes.c_double), ("beta", ctypes.c_double), ("c_max", ctypes.c_double),
+        ("u_wall", ctypes.c_double), ("F_ext_x", ctypes.c_double), ("F_ext_y", ctypes.c_double),
+        ("F_ext_z", ctypes.c_double), ("vel_period_T", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -98,6 +119,26 @@ def load(path: str = LIB_PATH):
     L.cmlb_destroy.restype = None
     for name in EXPORTS:
         if name not in ("cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    p3 = ctypes.POINTER(SimParams3)
+    L.cmlb3_create.argtypes = [p3, ctypes.c_int32, ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    L.cmlb3_init_fields.argtypes = [vp, ctypes.c_int32] + [dp] * 6
+    L.cmlb3_step.argtypes = [vp, ctypes.c_int32]
+    L.cmlb3_read_fields.argtypes = [vp, ctypes.c_int32] + [dp] * 6
+    L.cmlb3_inventory.argtypes = [vp, ctypes.c_int32, dp, dp]
+    L.cmlb3_get_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
+    L.cmlb3_set_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
+    L.cmlb3_fault_flags.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.cmlb3_synchronize.argtypes = [vp]
+    L.cmlb3_set_use_graph.argtypes = [vp, ctypes.c_int32]
+    L.cmlb3_step_count.argtypes = [vp]
+    L.cmlb3_step_count.restype = ctypes.c_int64
+    L.cmlb3_last_error.argtypes = [vp]
+    L.cmlb3_last_error.restype = ctypes.c_char_p
+    L.cmlb3_destroy.argtypes = [vp]
+    L.cmlb3_destroy.restype = None
+    for name in EXPORTS3:
+        if name not in ("cmlb3_step_count", "cmlb3_last_error", "cmlb3_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -272,3 +313,109 @@ class Context:
     @property
     def step_count(self):
         return self.L.cmlb_step_count(self.h)
+
+
+def make_params3(d: dict) -> SimParams3:
+    p = SimParams3()
+    for name, _ in SimParams3._fields_:
+        if name not in d:
+            continue
+        v = d[name]
+        if name == "bc_y" and isinstance(v, str):
+            v = BC[v]
+        if name == "flow" and isinstance(v, str):
+            v = FLOW[v]
+        setattr(p, name, v)
+    return p
+
+
+class Context3:
+    """A set of 3D (D3Q27) simulations advanced together by the HIP library.
+    ``params``: dicts keyed by ``cmlb3_sim_params`` names.  Fields are numpy
+    arrays [nz][ny][nx]; populations [27][nz][ny][nx]."""
+
+    def __init__(self, params, precision="fp64", stream=None):
+        if isinstance(params, dict):
+            params = [params]
+        self.L = load()
+        self.params = [dict(p) for p in params]
+        arr = (SimParams3 * len(params))(*[make_params3(p) for p in params])
+        self._arr = arr
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        rc = self.L.cmlb3_create(arr, len(params), prec, ctypes.c_void_p(stream or 0),
+                                 ctypes.byref(h))
+        if rc != OK:
+            raise CmlbError(rc, "cmlb3_create failed")
+        self.h = h
+        self.shapes = [(int(p["nz"]), int(p["ny"]), int(p["nx"])) for p in self.params]
+        fl = self.params[0].get("flow", 0)
+        self.coupled = (FLOW[fl] if isinstance(fl, str) else fl) == 2
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self.L.cmlb3_last_error(self.h)
+            raise CmlbError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cmlb3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_fields(self, sim, phi, c, ux=None, uy=None, uz=None, P=None):
+        sh = self.shapes[sim]
+        arrs = [_f64(v, sh) for v in (phi, c, ux, uy, uz, P)]
+        self._check(self.L.cmlb3_init_fields(self.h, sim, *[_dptr(a) for a in arrs]),
+                    "cmlb3_init_fields")
+
+    def step(self, n=1):
+        self._check(self.L.cmlb3_step(self.h, int(n)), "cmlb3_step")
+
+    def read_fields(self, sim=0):
+        sh = self.shapes[sim]
+        out = {k: np.zeros(sh) for k in ("phi", "c", "ux", "uy", "uz", "P")}
+        self._check(self.L.cmlb3_read_fields(self.h, sim, *[_dptr(out[k]) for k in (
+            "phi", "c", "ux", "uy", "uz", "P")]), "cmlb3_read_fields")
+        return out
+
+    def inventory(self, sim=0):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.cmlb3_inventory(self.h, sim, ctypes.byref(a), ctypes.byref(b)),
+                    "cmlb3_inventory")
+        return a.value, b.value
+
+    def get_populations(self, sim=0):
+        sh = (27,) + self.shapes[sim]
+        f, h = np.zeros(sh), np.zeros(sh)
+        g = np.zeros(sh) if self.coupled else None
+        self._check(self.L.cmlb3_get_populations(self.h, sim, _dptr(f), _dptr(h), _dptr(g)),
+                    "cmlb3_get_populations")
+        return f, h, g
+
+    def set_populations(self, sim, f, h, g=None):
+        sh = (27,) + self.shapes[sim]
+        f, h = _f64(f, sh), _f64(h, sh)
+        g = _f64(g, sh) if g is not None else None
+        self._check(self.L.cmlb3_set_populations(self.h, sim, _dptr(f), _dptr(h), _dptr(g)),
+                    "cmlb3_set_populations")
+
+    def fault_flags(self, sim=0):
+        v = ctypes.c_int32()
+        self._check(self.L.cmlb3_fault_flags(self.h, sim, ctypes.byref(v)), "cmlb3_fault_flags")
+        return v.value
+
+    def synchronize(self):
+        self._check(self.L.cmlb3_synchronize(self.h), "cmlb3_synchronize")
+
+    def set_use_graph(self, on):
+        self._check(self.L.cmlb3_set_use_graph(self.h, 1 if on else 0), "cmlb3_set_use_graph")
+
+    @property
+    def step_count(self):
+        return self.L.cmlb3_step_count(self.h)

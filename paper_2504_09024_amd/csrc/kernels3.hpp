@@ -1,0 +1,837 @@
+// HIP kernels of the three-dimensional (D3Q27) coupled central-moment LB
+// step for gfx950.  The paper states its schemes in 2D and only claims the
+// extension; the 3D scheme here takes each 2D step over axis by axis
+// (D3Q27 = D1Q3 x D1Q3 x D1Q3), with the readings listed in the design notes.
+//
+// A time step is two launches over a tile table of every simulation:
+//
+//   k_moments3  pull the 81 pre-collision populations of each node,
+//               q_a(x) = q~_a(x - e_a) (own opposite slot behind a wall),
+//               and keep only what the collision needs: zeroth and first
+//               moments of f and h, moments up to second order of g
+//               (18 values per node, in the compute type);
+//   k_collide3  per 64 x TY x TZ tile: phi (radius 2), c and P^ (radius 1)
+//               from the moment arrays into LDS, unit normals on the
+//               radius-1 region, then per node the interface geometry,
+//               Langmuir sigma(c), F_s, F_p, u, P and the three collisions;
+//               post-collision populations stored at the node (aligned).
+//
+// Splitting at the moments replaces the fused 2D kernel's halo ring, which
+// in 3D would pull 27 populations for 2-5 halo nodes per own node, by
+// coalesced reads of three compact fields; it costs 2 x 72 bytes per node
+// (FP32) on top of the 648 algorithmic bytes.
+//
+// Storage is the 2D library's: s_a = (q_a/w_a - q_ref) scale per population,
+// q_ref = phi_m (FP16 f), P_ref = rho_b cs2 (g), 0 otherwise.  Collisions
+// work on deviations from the rest state, so FP32 keeps its relative
+// precision on small velocities, and outputs are the node's own zeroth
+// moment plus a deviation, so a resting bulk node is a fixed point.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.hpp"
+
+namespace cmlb3 {
+
+using cmlb::Buf;
+using cmlb::CPOL_NT;
+using cmlb::fmix32;
+using cmlb::log_;
+using cmlb::make_rsrc;
+using cmlb::mirror_coord;
+using cmlb::rcp_;
+using cmlb::sqrt_;
+using cmlb::Store;
+using cmlb::weyl;
+using cmlb::wrap_coord;
+
+constexpr int FLOW_NONE = 0, FLOW_PRESCRIBED = 1, FLOW_COUPLED = 2;
+constexpr int NMOM = 18;         // moments kept per node
+constexpr int TXW = 64;          // tile width (one wavefront)
+constexpr int WG3 = 256;         // threads per block of the auxiliary kernels
+constexpr double NORMAL_EPS3 = 1e-12;
+
+template <class T>
+struct C3 {
+    static constexpr T cs2 = T(1) / T(3);
+    static constexpr T w0 = T(8) / T(27);    // rest
+    static constexpr T w1 = T(2) / T(27);    // faces
+    static constexpr T w2 = T(1) / T(54);    // edges
+    static constexpr T w3 = T(1) / T(216);   // corners
+};
+
+// Direction a = ix + 3 iy + 9 iz, i -> e: 0 -> 0, 1 -> +1, 2 -> -1.
+__device__ __forceinline__ constexpr int E1(int i) { return i == 0 ? 0 : (i == 1 ? 1 : -1); }
+__device__ __forceinline__ constexpr int EXd(int a) { return E1(a % 3); }
+__device__ __forceinline__ constexpr int EYd(int a) { return E1((a / 3) % 3); }
+__device__ __forceinline__ constexpr int EZd(int a) { return E1(a / 9); }
+__device__ __forceinline__ constexpr int OPPd(int a) {
+    // opposite component index: 0 -> 0, 1 <-> 2
+    return ((3 - a % 3) % 3) + 3 * ((3 - (a / 3) % 3) % 3) + 9 * ((3 - a / 9) % 3);
+}
+template <class T>
+__device__ __forceinline__ constexpr T wgt3(int a) {
+    const int n = (a % 3 != 0) + ((a / 3) % 3 != 0) + (a / 9 != 0);
+    return n == 0 ? C3<T>::w0 : (n == 1 ? C3<T>::w1 : (n == 2 ? C3<T>::w2 : C3<T>::w3));
+}
+template <class T>
+__device__ __forceinline__ constexpr T inv_wgt3(int a) {
+    const int n = (a % 3 != 0) + ((a / 3) % 3 != 0) + (a / 9 != 0);
+    return n == 0 ? T(27) / T(8) : (n == 1 ? T(27) / T(2) : (n == 2 ? T(54) : T(216)));
+}
+
+// Per-simulation constants in the compute type.
+template <class T>
+struct Consts3 {
+    T inv_f, qref_f, scale_f, inv_h, scale_h, inv_g, scale_g;
+    T phi_a, phi_b, inv_dphi, phim, theta_k, thetac_k;
+    T M_phi, D_s, omega_k, omega_c;
+    T rho_b, drho, nu_b, dnu, inv_rho_b, omega_nu_b, omega_zeta;
+    T sigma0, beta, c_max, inv_cmax, ks, u_wall, Fx, Fy, Fz, P_ref, dr_cs2;
+};
+
+struct SimDev3 {
+    int32_t nx, ny, nz;
+    int32_t tile0, ntiles;
+    int32_t uniform_rho, uniform_nu;
+    int32_t pad_;
+    int64_t off;         // element offset of this sim's populations (3 x 27 planes)
+    int64_t moff;        // element offset of its moments (18 planes)
+    int64_t uoff;        // element offset of its prescribed velocity shapes (3 planes)
+    uint32_t node_base;  // first global node index (stochastic-rounding seed)
+    uint32_t pad2_;
+    double vel_period_T;
+    Consts3<double> kd;
+    Consts3<float> kf;
+};
+
+template <class T>
+__device__ __forceinline__ const Consts3<T>& consts3(const SimDev3* sd);
+template <>
+__device__ __forceinline__ const Consts3<double>& consts3<double>(const SimDev3* sd) {
+    return sd->kd;
+}
+template <>
+__device__ __forceinline__ const Consts3<float>& consts3<float>(const SimDev3* sd) {
+    return sd->kf;
+}
+
+struct StepArgs3 {
+    const void* src;       // populations read (pre-collision, pull form)
+    void* dst;             // populations written
+    void* mom;             // moments arena (compute type)
+    const SimDev3* sims;
+    const int4* tiles;     // (sim, x0, y0, z0)
+    int32_t tile_base, ntiles;
+    int32_t xcd_remap, pad_;
+    const void* ushape;    // prescribed velocity shapes, compute type
+    const int64_t* step_in;
+    int64_t* step_out;
+    int32_t* fault;
+    double* fields_out;    // fields mode: [6][nz][ny][nx] (phi, c, ux, uy, uz, P)
+};
+
+__device__ __forceinline__ int tile_index(const StepArgs3& a) {
+    int tix = blockIdx.x;
+    if (a.xcd_remap) {
+        // XCD k (blocks k, k+8, ...) takes the contiguous tile range
+        // [k*per, (k+1)*per), so neighbouring tiles share one L2
+        const int per = (int)gridDim.x >> 3;
+        tix = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    }
+    return tix;
+}
+
+// ---------------------------------------------------------------------------
+// k_moments3: pulled populations -> moments.
+// Tile = 64 x MT_ROWS nodes (x by (y, z) rows); block = 256 threads.
+// Moment planes (per node, compute type):
+//   0 f zeroth (storage units), 1-3 f first (true units),
+//   4 h zeroth (storage units), 5-7 h first,
+//   8 g zeroth of the deviation (P^ - P_ref), 9-11 g first,
+//   12-14 g second diagonal (xx, yy, zz), 15-17 g second off-diagonal
+//   (xy, xz, yz), all of the deviations d_a = g_a - w_a P_ref.
+// ---------------------------------------------------------------------------
+constexpr int MT_ROWS = 4;  // (y, z) rows per moments tile
+
+template <class S, class T, bool WALLS>
+__device__ __forceinline__ void pull27(__amdgpu_buffer_rsrc_t r, int pb, int x, int y, int z,
+                                       int nx, int ny, int nz, bool inner, T v[27]) {
+    constexpr int SB = sizeof(S);
+    const int plane = nx * ny;
+    if (inner) {
+        const int vo = ((z * ny + y) * nx + x) * SB;
+#pragma unroll
+        for (int a = 0; a < 27; ++a) {
+            const int so = a * pb - (EXd(a) + EYd(a) * nx + EZd(a) * plane) * SB;
+            v[a] = T(Buf<S>::load(r, vo, so));
+        }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 27; ++a) {
+        int sx = x - EXd(a), sy = y - EYd(a), sz = z - EZd(a), pa = a;
+        sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+        sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+        if (sy < 0 || sy >= ny) {
+            if (WALLS) {
+                pa = OPPd(a);
+                sx = x;
+                sy = y;
+                sz = z;
+            } else {
+                sy = sy < 0 ? sy + ny : sy - ny;
+            }
+        }
+        // the plane varies per lane at a wall, so it goes into the vector offset
+        v[a] = T(Buf<S>::load(r, ((sz * ny + sy) * nx + sx) * SB + pa * pb, 0));
+    }
+}
+
+// zeroth (exact for a uniform node: s0 + sum w (s_a - s0)) and first
+// moments of stored scalar-lattice values, storage units
+template <class T>
+__device__ __forceinline__ void scalar_moments27(const T v[27], T& m0, T& jx, T& jy, T& jz) {
+#pragma clang fp contract(off)
+    const T s0 = v[0];
+    T z = T(0), x = T(0), y = T(0), w = T(0);
+#pragma unroll
+    for (int a = 1; a < 27; ++a) {
+        const T d = wgt3<T>(a) * (v[a] - s0);
+        z += d;
+        if (EXd(a)) x += EXd(a) > 0 ? d : -d;
+        if (EYd(a)) y += EYd(a) > 0 ? d : -d;
+        if (EZd(a)) w += EZd(a) > 0 ? d : -d;
+    }
+    m0 = s0 + z;
+    jx = x;
+    jy = y;
+    jz = w;
+}
+
+template <class S, class T, int FLOW, bool WALLS>
+__global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
+    const int tix = tile_index(a);
+    if (tix >= a.ntiles) return;
+    const int4 tl = a.tiles[a.tile_base + tix];
+    const SimDev3* sd = a.sims + tl.x;
+    const Consts3<T>& k = consts3<T>(sd);
+    const int nx = sd->nx, ny = sd->ny, nz = sd->nz;
+    // a moments tile is 64 columns of MT_ROWS consecutive (y, z) rows,
+    // rows numbered z ny + y; tl.z is its first row
+    const int x = tl.y + (int)(threadIdx.x & 63);
+    const int rr = tl.z + (int)(threadIdx.x >> 6);
+    if (x >= nx || rr >= ny * nz) return;
+    const int y = rr % ny, z = rr / ny;
+    constexpr int SB = sizeof(S);
+    constexpr bool CPL = FLOW == FLOW_COUPLED;
+    const int plane = nx * ny;
+    const int vol = plane * nz;
+    const int pb = vol * SB;
+    const int lb = 27 * pb;
+    const char* srcb = static_cast<const char*>(a.src) + sd->off * SB;
+    const bool inner = x >= 1 && x + 1 < nx && y >= 1 && y + 1 < ny && z >= 1 && z + 1 < nz;
+    T* mom = static_cast<T*>(a.mom) + sd->moff + ((z * ny + y) * nx + x);
+    T v[27];
+    T m0, jx, jy, jz;
+    pull27<S, T, WALLS>(make_rsrc(srcb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+    scalar_moments27(v, m0, jx, jy, jz);
+    mom[0] = m0;
+    mom[vol] = jx * k.inv_f;
+    mom[2 * vol] = jy * k.inv_f;
+    mom[3 * vol] = jz * k.inv_f;
+    pull27<S, T, WALLS>(make_rsrc(srcb + lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+    scalar_moments27(v, m0, jx, jy, jz);
+    mom[4 * vol] = m0;
+    mom[5 * vol] = jx * k.inv_h;
+    mom[6 * vol] = jy * k.inv_h;
+    mom[7 * vol] = jz * k.inv_h;
+    if constexpr (CPL) {
+        pull27<S, T, WALLS>(make_rsrc(srcb + 2 * lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+        // deviations d_a = w_a s_a / scale and their raw moments
+        T r0 = T(0), r1[3] = {T(0), T(0), T(0)}, r2[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                const T d = Store<S>::scaled ? wgt3<T>(q) * (v[q] * k.inv_g) : wgt3<T>(q) * v[q];
+                const int ex = EXd(q), ey = EYd(q), ez = EZd(q);
+                r0 += d;
+                if (ex) r1[0] += ex > 0 ? d : -d;
+                if (ey) r1[1] += ey > 0 ? d : -d;
+                if (ez) r1[2] += ez > 0 ? d : -d;
+                if (ex) r2[0] += d;
+                if (ey) r2[1] += d;
+                if (ez) r2[2] += d;
+                if (ex && ey) r2[3] += ex * ey > 0 ? d : -d;
+                if (ex && ez) r2[4] += ex * ez > 0 ? d : -d;
+                if (ey && ez) r2[5] += ey * ez > 0 ? d : -d;
+            }
+        }
+        mom[8 * vol] = r0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) mom[(9 + i) * vol] = r1[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) mom[(12 + i) * vol] = r2[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Axis-wise inverse of the central-moment map.  t[i + 3j + 9k] holds central
+// moments with exponents (i, j, k) on entry and populations with components
+// (E1(i), E1(j), E1(k)) on exit.  One axis: central -> raw
+// (r0 = k0, r1 = k1 + u k0, r2 = k2 + 2u k1 + u^2 k0), raw -> populations
+// (q0 = r0 - r2, q+ = (r2 + r1)/2, q- = (r2 - r1)/2).
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void axis_inv(T& a0, T& a1, T& a2, T u, T u2) {
+    const T r1 = a1 + u * a0;
+    const T r2 = a2 + T(2) * u * a1 + u2 * a0;
+    a0 = a0 - r2;
+    a1 = T(0.5) * (r2 + r1);
+    a2 = T(0.5) * (r2 - r1);
+}
+template <class T>
+__device__ __forceinline__ void inverse27(T t[27], T ux, T uy, T uz) {
+    const T ux2 = ux * ux, uy2 = uy * uy, uz2 = uz * uz;
+#pragma unroll
+    for (int b = 0; b < 27; b += 3) axis_inv(t[b], t[b + 1], t[b + 2], ux, ux2);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int b = i + 9 * k;
+            axis_inv(t[b], t[b + 3], t[b + 6], uy, uy2);
+        }
+#pragma unroll
+    for (int b = 0; b < 9; ++b) axis_inv(t[b], t[b + 9], t[b + 18], uz, uz2);
+}
+
+// rest-state central moments: c(0) = 1, c(1) = 0, c(2) = cs2; central
+// moments of a rest distribution about u: m(0) = 1, m(1) = -u, m(2) = cs2 + u^2
+template <class T>
+__device__ __forceinline__ T crest3(int a) {
+    return a == 0 ? T(1) : (a == 1 ? T(0) : C3<T>::cs2);
+}
+
+// Scalar lattice (f or h): deviation of the post-collision central moments
+// from those of the rest distribution s w_a about u, then populations:
+// out_a = q~_a - w_a s.
+template <class T, bool MOV>
+__device__ __forceinline__ void scalar_dev27(T s, T k1x, T k1y, T k1z, T ux, T uy, T uz,
+                                             T t[27]) {
+    const T mx[3] = {T(1), -ux, C3<T>::cs2 + ux * ux};
+    const T my[3] = {T(1), -uy, C3<T>::cs2 + uy * uy};
+    const T mz[3] = {T(1), -uz, C3<T>::cs2 + uz * uz};
+#pragma unroll
+    for (int m = 0; m < 27; ++m) {
+        const int a = m % 3, b = (m / 3) % 3, c = m / 9;
+        const int order = a + b + c;
+        if (order == 0) {
+            t[m] = T(0);
+        } else if (order == 1) {
+            const T k1 = a ? k1x : (b ? k1y : k1z);
+            const T u = a ? ux : (b ? uy : uz);
+            t[m] = k1 + s * u;
+        } else if (!MOV) {
+            t[m] = T(0);  // u = 0: rest moments are the equilibrium ones
+        } else {
+            t[m] = s * (crest3<T>(a) * crest3<T>(b) * crest3<T>(c) - mx[a] * my[b] * mz[c]);
+        }
+    }
+    inverse27(t, ux, uy, uz);
+}
+
+// Flow lattice: post-collision central moments minus P_ref times those of
+// the rest distribution, i.e. of the deviations d~_a = g~_a - w_a P_ref.
+// eta2[6]: second-order central moments of the deviations (xx, yy, zz, xy,
+// xz, yz); dP = P - P_ref; fp = F_p, ft = F_t, gam = F_p . u.
+template <class T>
+__device__ __forceinline__ void flow_dev27(const T eta2[6], T dP, T rho, T ux, T uy, T uz,
+                                           const T fp[3], const T ft[3], T gam, T om_zeta,
+                                           T om_nu, T t[27]) {
+    const T cs2 = C3<T>::cs2;
+    const T u[3] = {ux, uy, uz};
+    const T mx[3] = {T(1), -ux, cs2 + ux * ux};
+    const T my[3] = {T(1), -uy, cs2 + uy * uy};
+    const T mz[3] = {T(1), -uz, cs2 + uz * uz};
+    const T rc = rho * cs2;
+    // equilibrium deviation: dP prod m + rho cs2 (prod c - prod m)
+#pragma unroll
+    for (int m = 0; m < 27; ++m) {
+        const int a = m % 3, b = (m / 3) % 3, c = m / 9;
+        const T pm = mx[a] * my[b] * mz[c];
+        t[m] = dP * pm + rc * (crest3<T>(a) * crest3<T>(b) * crest3<T>(c) - pm);
+    }
+    // sources (zero from third order on)
+    T src[10];
+    src[0] = gam;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) src[1 + i] = cs2 * ft[i] - u[i] * gam;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) src[4 + i] = T(2) * cs2 * fp[i] * u[i] + (u[i] * u[i] + cs2) * gam;
+    src[7] = cs2 * (fp[0] * u[1] + fp[1] * u[0]) + u[0] * u[1] * gam;
+    src[8] = cs2 * (fp[0] * u[2] + fp[2] * u[0]) + u[0] * u[2] * gam;
+    src[9] = cs2 * (fp[1] * u[2] + fp[2] * u[1]) + u[1] * u[2] * gam;
+    // rate 1 on orders 0 and 1: eq + src/2
+    t[0] += T(0.5) * src[0];
+    t[1] += T(0.5) * src[1];
+    t[3] += T(0.5) * src[2];
+    t[9] += T(0.5) * src[3];
+    // second order: off-diagonal and deviatoric parts at omega_nu, trace at
+    // omega_zeta
+    const int od[3] = {4, 10, 12};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int m = od[i];
+        t[m] = eta2[3 + i] + om_nu * (t[m] - eta2[3 + i]) + (T(1) - T(0.5) * om_nu) * src[7 + i];
+    }
+    const int dg[3] = {2, 6, 18};
+    const T tr = eta2[0] + eta2[1] + eta2[2];
+    const T tre = t[2] + t[6] + t[18];
+    const T trs = src[4] + src[5] + src[6];
+    const T trt = tr + om_zeta * (tre - tr) + (T(1) - T(0.5) * om_zeta) * trs;
+    const T third = T(1) / T(3);
+    T dd[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T d = eta2[i] - third * tr, de = t[dg[i]] - third * tre, ds = src[4 + i] - third * trs;
+        dd[i] = d + om_nu * (de - d) + (T(1) - T(0.5) * om_nu) * ds;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t[dg[i]] = dd[i] + third * trt;
+    inverse27(t, ux, uy, uz);
+}
+
+// Isotropic D3Q27 gradient from an LDS box of row pitch PX and plane pitch
+// PXY: d_i = (1/cs2) sum_a w_a e_ai F(x + e_a).
+template <class T, int PX, int PXY>
+__device__ __forceinline__ void lds_grad3(const T* L, int idx, T& gx, T& gy, T& gz) {
+    T sx = T(0), sy = T(0), sz = T(0);
+#pragma unroll
+    for (int a = 1; a < 27; ++a) {
+        const int ex = EXd(a), ey = EYd(a), ez = EZd(a);
+        const T v = wgt3<T>(a) * L[idx + ex + ey * PX + ez * PXY];
+        if (ex) sx += ex > 0 ? v : -v;
+        if (ey) sy += ey > 0 ? v : -v;
+        if (ez) sz += ez > 0 ? v : -v;
+    }
+    gx = T(3) * sx;
+    gy = T(3) * sy;
+    gz = T(3) * sz;
+}
+
+// ---------------------------------------------------------------------------
+// k_collide3: tile 64 x TY x TZ, one node per thread (NW = TY*TZ waves).
+// ---------------------------------------------------------------------------
+template <class T, int NW>
+struct Occ3 {
+    static constexpr int waves_per_eu = sizeof(T) == 4 ? 2 : 1;
+};
+
+template <class S, class T, int FLOW, bool WALLS, int TY, int TZ, bool FIELDS, bool NTS>
+__global__ __launch_bounds__(TY* TZ * 64, (Occ3<T, TY * TZ>::waves_per_eu)) void k_collide3(
+    const StepArgs3 a) {
+    constexpr int NT = TY * TZ * 64;
+    constexpr int CP = NTS ? CPOL_NT : 0;
+    constexpr bool CPL = FLOW == FLOW_COUPLED;
+    constexpr bool MOV = FLOW != FLOW_NONE;
+    constexpr int PX = TXW + 4, PY = TY + 4, PZ = TZ + 4;  // phi box (radius 2)
+    constexpr int QX = TXW + 2, QY = TY + 2, QZ = TZ + 2;  // c, P^, n box (radius 1)
+    constexpr int SB = sizeof(S);
+    __shared__ T phiL[PX * PY * PZ];
+    __shared__ T cL[QX * QY * QZ];
+    __shared__ T pL[CPL ? QX * QY * QZ : 1];
+    __shared__ T nL[CPL ? 3 * QX * QY * QZ : 1];
+
+    const int tix = tile_index(a);
+    if (tix >= a.ntiles) return;
+    const int4 tl = a.tiles[a.tile_base + tix];
+    const SimDev3* sd = a.sims + tl.x;
+    const Consts3<T>& k = consts3<T>(sd);
+    const int nx = sd->nx, ny = sd->ny, nz = sd->nz;
+    const int x0 = tl.y, y0 = tl.z, z0 = tl.w;
+    const int plane = nx * ny, vol = plane * nz;
+    const T* mom = static_cast<const T*>(a.mom) + sd->moff;
+    const int64_t step = *a.step_in;
+    const int tid = threadIdx.x;
+
+    // ---------------- LDS boxes from the moment arrays ---------------------
+    for (int i = tid; i < PX * PY * PZ; i += NT) {
+        const int rz = i / (PX * PY), rem = i - rz * PX * PY, ry = rem / PX, rx = rem - ry * PX;
+        const int gx = wrap_coord(x0 - 2 + rx, nx);
+        const int gy = WALLS ? mirror_coord(y0 - 2 + ry, ny) : wrap_coord(y0 - 2 + ry, ny);
+        const int gz = wrap_coord(z0 - 2 + rz, nz);
+        const int n = (gz * ny + gy) * nx + gx;
+        phiL[i] = mom[n] * k.inv_f + k.qref_f;
+        const bool r1 = rx >= 1 && rx <= PX - 2 && ry >= 1 && ry <= PY - 2 && rz >= 1 && rz <= PZ - 2;
+        if (r1) {
+            const int q = ((rz - 1) * QY + (ry - 1)) * QX + (rx - 1);
+            cL[q] = mom[4 * vol + n] * k.inv_h;
+            if constexpr (CPL) pL[q] = mom[8 * vol + n];
+        }
+    }
+    __syncthreads();
+    if constexpr (CPL) {
+        for (int i = tid; i < QX * QY * QZ; i += NT) {
+            const int qz = i / (QX * QY), rem = i - qz * QX * QY, qy = rem / QX, qx = rem - qy * QX;
+            T gx, gy, gz;
+            lds_grad3<T, PX, PX * PY>(phiL, ((qz + 1) * PY + qy + 1) * PX + qx + 1, gx, gy, gz);
+            const T inv = rcp_(sqrt_(gx * gx + gy * gy + gz * gz) + T(NORMAL_EPS3));
+            nL[i] = gx * inv;
+            nL[QX * QY * QZ + i] = gy * inv;
+            nL[2 * QX * QY * QZ + i] = gz * inv;
+        }
+        __syncthreads();
+    }
+
+    // ---------------- per node ---------------------------------------------
+    const int lx = tid & 63, r = tid >> 6;
+    const int ly = r % TY, lz = r / TY;
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    const bool valid = gx < nx && gy < ny && gz < nz;
+    if (!valid) return;
+    const int own = (gz * ny + gy) * nx + gx;
+    const int pidx = ((lz + 2) * PY + ly + 2) * PX + lx + 2;
+    const int qidx = ((lz + 1) * QY + ly + 1) * QX + lx + 1;
+    const T phi = phiL[pidx], c = cL[qidx];
+    T gpx, gpy, gpz;
+    lds_grad3<T, PX, PX * PY>(phiL, pidx, gpx, gpy, gpz);
+    const T gm2 = gpx * gpx + gpy * gpy + gpz * gpz;
+    T nxv, nyv, nzv;
+    if constexpr (CPL) {
+        nxv = nL[qidx];
+        nyv = nL[QX * QY * QZ + qidx];
+        nzv = nL[2 * QX * QY * QZ + qidx];
+    } else {
+        const T inv = rcp_(sqrt_(gm2) + T(NORMAL_EPS3));
+        nxv = gpx * inv;
+        nyv = gpy * inv;
+        nzv = gpz * inv;
+    }
+    const T theta = k.theta_k * (k.phi_a - phi) * (phi - k.phi_b) * k.inv_dphi;
+    const T theta_c = k.thetac_k * c * (k.phim - phi) * k.inv_dphi;
+    T ux = T(0), uy = T(0), uz = T(0), dP = T(0), rho = T(1), om_nu = T(1);
+    T fp[3] = {T(0), T(0), T(0)}, ft[3] = {T(0), T(0), T(0)}, gam = T(0);
+    int fault = 0;
+    if constexpr (CPL) {
+        T dn[9], gc[3], gq[3];
+        lds_grad3<T, QX, QX * QY>(nL, qidx, dn[0], dn[1], dn[2]);
+        lds_grad3<T, QX, QX * QY>(nL + QX * QY * QZ, qidx, dn[3], dn[4], dn[5]);
+        lds_grad3<T, QX, QX * QY>(nL + 2 * QX * QY * QZ, qidx, dn[6], dn[7], dn[8]);
+        lds_grad3<T, QX, QX * QY>(cL, qidx, gc[0], gc[1], gc[2]);
+        lds_grad3<T, QX, QX * QY>(pL, qidx, gq[0], gq[1], gq[2]);
+        const T curv = dn[0] + dn[4] + dn[8];
+        const T lam = (phi - k.phi_b) * k.inv_dphi;
+        rho = sd->uniform_rho ? k.rho_b : k.rho_b + lam * k.drho;
+        const T inv_rho = sd->uniform_rho ? k.inv_rho_b : rcp_(rho);
+        om_nu = sd->uniform_nu ? k.omega_nu_b : rcp_(T(3) * (k.nu_b + lam * k.dnu) + T(0.5));
+        const T arg = T(1) - c * k.inv_cmax;
+        const T sigma = k.sigma0 * (T(1) + k.beta * log_(arg));
+        if (!(arg > T(0)) || !(sigma >= T(0))) fault |= 2;
+        const T dsig = -k.sigma0 * k.beta * rcp_(k.c_max - c);
+        const T gs[3] = {dsig * gc[0], dsig * gc[1], dsig * gc[2]};
+        const T n3[3] = {nxv, nyv, nzv};
+        const T nd = nxv * gs[0] + nyv * gs[1] + nzv * gs[2];
+        const T wk = k.ks * gm2;
+        const T fe[3] = {k.Fx, k.Fy, k.Fz};
+        const T gp[3] = {gpx, gpy, gpz};
+        const T j[3] = {mom[9 * vol + own], mom[10 * vol + own], mom[11 * vol + own]};
+        T u[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ft[i] = wk * ((gs[i] - n3[i] * nd) - sigma * curv * n3[i]) + fe[i];
+            // F_p = -grad psi^, psi^ = P^ - rho cs2, rho linear in phi
+            fp[i] = -(gq[i] - k.dr_cs2 * gp[i]);
+            u[i] = (T(3) * j[i] + T(0.5) * ft[i]) * inv_rho;
+        }
+        ux = u[0];
+        uy = u[1];
+        uz = u[2];
+        gam = fp[0] * ux + fp[1] * uy + fp[2] * uz;
+        dP = mom[8 * vol + own] + T(0.5) * gam;
+    } else if constexpr (FLOW == FLOW_PRESCRIBED) {
+        const T tf = sd->vel_period_T != 0.0 ? T(cos(M_PI * (double)step / sd->vel_period_T)) : T(1);
+        const T* us = static_cast<const T*>(a.ushape) + sd->uoff;
+        ux = us[own] * tf;
+        uy = us[vol + own] * tf;
+        uz = us[2 * vol + own] * tf;
+    }
+    if (!isfinite(phi + c + ux + uy + uz + dP)) fault |= 1;
+    if (fault) atomicOr(a.fault + tl.x, fault);
+
+    if constexpr (FIELDS) {
+        double* o = a.fields_out;
+        o[own] = double(phi);
+        o[vol + own] = double(c);
+        o[2 * vol + own] = double(ux);
+        o[3 * vol + own] = double(uy);
+        o[4 * vol + own] = double(uz);
+        o[5 * vol + own] = CPL ? double(k.P_ref) + double(dP) : 0.0;
+        return;
+    } else {
+        if (blockIdx.x == 0 && tid == 0) *a.step_out = step + 1;
+        const int lb = 27 * vol * SB;
+        char* dstb = static_cast<char*>(a.dst) + sd->off * SB;
+        const int vo = own * SB;
+        const int pb = vol * SB;
+        uint32_t rs = 0;
+        if constexpr (Store<S>::scaled) {
+            const uint32_t key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
+            rs = fmix32(sd->node_base + (uint32_t)own) ^ key;
+        }
+        T t[27];
+        // f: phase field
+        {
+            const T m0 = mom[own];
+            const T jx = mom[vol + own], jy = mom[2 * vol + own], jz = mom[3 * vol + own];
+            const T om = k.omega_k, mt = k.M_phi * theta;
+            const T k1x = (T(1) - om) * (jx - ux * phi) + om * mt * nxv;
+            const T k1y = (T(1) - om) * (jy - uy * phi) + om * mt * nyv;
+            const T k1z = (T(1) - om) * (jz - uz * phi) + om * mt * nzv;
+            scalar_dev27<T, MOV>(phi, k1x, k1y, k1z, ux, uy, uz, t);
+            const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb, lb);
+#pragma unroll
+            for (int q = 0; q < 27; ++q)
+                Buf<S>::template store<CP>(w, vo, q * pb, m0 + k.scale_f * t[q] * inv_wgt3<T>(q),
+                                           rs + weyl(3 * q));
+        }
+        // h: surfactant
+        {
+            const T m0 = mom[4 * vol + own];
+            const T jx = mom[5 * vol + own], jy = mom[6 * vol + own], jz = mom[7 * vol + own];
+            const T om = k.omega_c, mt = k.D_s * theta_c;
+            const T k1x = (T(1) - om) * (jx - ux * c) + om * mt * nxv;
+            const T k1y = (T(1) - om) * (jy - uy * c) + om * mt * nyv;
+            const T k1z = (T(1) - om) * (jz - uz * c) + om * mt * nzv;
+            scalar_dev27<T, MOV>(c, k1x, k1y, k1z, ux, uy, uz, t);
+            const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + lb, lb);
+#pragma unroll
+            for (int q = 0; q < 27; ++q)
+                Buf<S>::template store<CP>(w, vo, q * pb, m0 + k.scale_h * t[q] * inv_wgt3<T>(q),
+                                           rs + weyl(3 * q + 1));
+        }
+        // g: flow
+        if constexpr (CPL) {
+            const T r0 = mom[8 * vol + own];
+            const T j[3] = {mom[9 * vol + own], mom[10 * vol + own], mom[11 * vol + own]};
+            T r2[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) r2[i] = mom[(12 + i) * vol + own];
+            // central second moments of the deviations about u
+            const T u[3] = {ux, uy, uz};
+            T eta2[6];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) eta2[i] = r2[i] - T(2) * u[i] * j[i] + u[i] * u[i] * r0;
+            eta2[3] = r2[3] - u[0] * j[1] - u[1] * j[0] + u[0] * u[1] * r0;
+            eta2[4] = r2[4] - u[0] * j[2] - u[2] * j[0] + u[0] * u[2] * r0;
+            eta2[5] = r2[5] - u[1] * j[2] - u[2] * j[1] + u[1] * u[2] * r0;
+            flow_dev27<T>(eta2, dP, rho, ux, uy, uz, fp, ft, gam, k.omega_zeta, om_nu, t);
+            // moving wall: slots of directions pointing into the wall are
+            // pulled back by this node next step; add 2 rho (e_opp . u_w)
+            T wcorr = T(0);
+            int wdir = 0;
+            if (WALLS) {
+                if (gy == 0) {
+                    wdir = -1;
+                    wcorr = T(2) * rho * k.u_wall * k.scale_g;
+                }
+                if (gy == ny - 1) {
+                    wdir = 1;
+                    wcorr = -T(2) * rho * k.u_wall * k.scale_g;
+                }
+            }
+            const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + 2 * lb, lb);
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                T v = k.scale_g * t[q] * inv_wgt3<T>(q);
+                if (WALLS && wdir != 0 && EYd(q) == wdir) v += wcorr * T(EXd(q));
+                Buf<S>::template store<CP>(w, vo, q * pb, v, rs + weyl(3 * q + 2));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation: populations at the central-moment equilibria of given
+// fields (FP64), each direction written into the slot it is pulled from.
+// ---------------------------------------------------------------------------
+struct InitArgs3 {
+    void* pop;              // sim's population block
+    const SimDev3* sd;
+    const double* phi;
+    const double* c;
+    const double* ux;       // may be null
+    const double* uy;
+    const double* uz;
+    const double* P;        // may be null
+    void* ushape;           // prescribed shapes (compute type), may be null
+    int32_t flow, walls;
+};
+
+// Pull slot of direction a at node (x, y, z): (plane, node index).
+__device__ __forceinline__ void pull_slot3(int x, int y, int z, int a, int nx, int ny, int nz,
+                                           bool walls, int& pa, int& node) {
+    int sx = x - EXd(a), sy = y - EYd(a), sz = z - EZd(a);
+    pa = a;
+    sx = wrap_coord(sx, nx);
+    sz = wrap_coord(sz, nz);
+    if (sy < 0 || sy >= ny) {
+        if (walls) {
+            pa = OPPd(a);
+            sx = x;
+            sy = y;
+            sz = z;
+        } else {
+            sy = wrap_coord(sy, ny);
+        }
+    }
+    node = (sz * ny + sy) * nx + sx;
+}
+
+template <class S, class T>
+__device__ __forceinline__ void encode_store(S* base, int64_t idx, double v) {
+    base[idx] = S(T(v));
+}
+
+template <class S, class T>
+__global__ __launch_bounds__(WG3) void k_init3(const InitArgs3 a) {
+    const SimDev3* sd = a.sd;
+    const int nx = sd->nx, ny = sd->ny, nz = sd->nz, plane = nx * ny, vol = plane * nz;
+    const int i = blockIdx.x * WG3 + threadIdx.x;
+    if (i >= vol) return;
+    const int x = i % nx, y = (i / nx) % ny, z = i / plane;
+    const Consts3<double>& k = sd->kd;
+    // isotropic gradient of phi with the step's ghost rules
+    double g[3] = {0.0, 0.0, 0.0};
+    for (int q = 1; q < 27; ++q) {
+        const int xx = wrap_coord(x + EXd(q), nx);
+        const int yy = a.walls ? mirror_coord(y + EYd(q), ny) : wrap_coord(y + EYd(q), ny);
+        const int zz = wrap_coord(z + EZd(q), nz);
+        const double v = wgt3<double>(q) * a.phi[(zz * ny + yy) * nx + xx];
+        g[0] += EXd(q) * v;
+        g[1] += EYd(q) * v;
+        g[2] += EZd(q) * v;
+    }
+    for (int d = 0; d < 3; ++d) g[d] *= 3.0;
+    const double inv = 1.0 / (sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) + NORMAL_EPS3);
+    const double n3[3] = {g[0] * inv, g[1] * inv, g[2] * inv};
+    const double phi = a.phi[i], c = a.c[i];
+    const double u[3] = {a.ux ? a.ux[i] : 0.0, a.uy ? a.uy[i] : 0.0, a.uz ? a.uz[i] : 0.0};
+    const double theta = k.theta_k * (k.phi_a - phi) * (phi - k.phi_b) * k.inv_dphi;
+    const double theta_c = k.thetac_k * c * (k.phim - phi) * k.inv_dphi;
+    S* pop = static_cast<S*>(a.pop);
+    double t[27];
+    // f and h: deviations from the rest distribution about u, then storage
+    for (int lat = 0; lat < 2; ++lat) {
+        const double s = lat == 0 ? phi : c;
+        const double jm = lat == 0 ? k.M_phi * theta : k.D_s * theta_c;
+        scalar_dev27<double, true>(s, jm * n3[0], jm * n3[1], jm * n3[2], u[0], u[1], u[2], t);
+        const double qref = lat == 0 ? k.qref_f : 0.0;
+        const double scale = lat == 0 ? k.scale_f : k.scale_h;
+        for (int q = 0; q < 27; ++q) {
+            int pa, node;
+            pull_slot3(x, y, z, q, nx, ny, nz, a.walls, pa, node);
+            const double v = ((s - qref) + t[q] * inv_wgt3<double>(q)) * scale;
+            encode_store<S, T>(pop, (int64_t)(lat * 27 + pa) * vol + node, v);
+        }
+    }
+    if (a.flow == FLOW_COUPLED) {
+        const double lam = (phi - k.phi_b) * k.inv_dphi;
+        const double rho = k.rho_b + lam * k.drho;
+        const double P = a.P ? a.P[i] : rho * C3<double>::cs2;
+        const double dP = P - k.P_ref;
+        const double mx[3] = {1.0, -u[0], C3<double>::cs2 + u[0] * u[0]};
+        const double my[3] = {1.0, -u[1], C3<double>::cs2 + u[1] * u[1]};
+        const double mz[3] = {1.0, -u[2], C3<double>::cs2 + u[2] * u[2]};
+        for (int m = 0; m < 27; ++m) {
+            const int p = m % 3, q = (m / 3) % 3, r = m / 9;
+            const double pm = mx[p] * my[q] * mz[r];
+            t[m] = dP * pm + rho * C3<double>::cs2 *
+                                 (crest3<double>(p) * crest3<double>(q) * crest3<double>(r) - pm);
+        }
+        inverse27(t, u[0], u[1], u[2]);
+        for (int q = 0; q < 27; ++q) {
+            int pa, node;
+            pull_slot3(x, y, z, q, nx, ny, nz, a.walls, pa, node);
+            encode_store<S, T>(pop, (int64_t)(54 + pa) * vol + node,
+                               t[q] * inv_wgt3<double>(q) * k.scale_g);
+        }
+    }
+    if (a.flow == FLOW_PRESCRIBED && a.ushape) {
+        T* us = static_cast<T*>(a.ushape);
+        us[i] = T(u[0]);
+        us[vol + i] = T(u[1]);
+        us[2 * vol + i] = T(u[2]);
+    }
+}
+
+// Decode (dir = 0) or encode (dir = 1) the pre-collision populations of one
+// simulation between storage and FP64 host order [lat][27][nz][ny][nx].
+template <class S, class T>
+__global__ __launch_bounds__(WG3) void k_transfer3(void* pop, const SimDev3* sd, double* host,
+                                                   int lattices, int walls, int dir) {
+    const int nx = sd->nx, ny = sd->ny, nz = sd->nz, vol = nx * ny * nz;
+    const int64_t i = (int64_t)blockIdx.x * WG3 + threadIdx.x;
+    if (i >= (int64_t)lattices * 27 * vol) return;
+    const int lat = (int)(i / (27 * (int64_t)vol));
+    const int q = (int)((i / vol) % 27);
+    const int n = (int)(i % vol);
+    const int x = n % nx, y = (n / nx) % ny, z = n / (nx * ny);
+    int pa, node;
+    pull_slot3(x, y, z, q, nx, ny, nz, walls, pa, node);
+    const Consts3<double>& k = sd->kd;
+    const double scale = lat == 0 ? k.scale_f : (lat == 1 ? k.scale_h : k.scale_g);
+    const double qref = lat == 0 ? k.qref_f : (lat == 1 ? 0.0 : k.P_ref);
+    const double w = wgt3<double>(q);
+    S* p = static_cast<S*>(pop) + (int64_t)(lat * 27 + pa) * vol + node;
+    if (dir == 0) {
+        host[i] = w * (double(*p) / scale + qref);
+    } else {
+        *p = S(T((host[i] / w - qref) * scale));
+    }
+}
+
+// Inventory: FP64 sums of all stored f and h populations (decoded), per
+// (y, z) row then over rows in a fixed order.
+template <class S>
+__global__ __launch_bounds__(WG3) void k_inventory_rows3(const void* pop, const SimDev3* sd,
+                                                         double* rows) {
+    const int nx = sd->nx, ny = sd->ny, nz = sd->nz, vol = nx * ny * nz;
+    const int row = blockIdx.x;  // y + ny z
+    const int lat = blockIdx.y;  // 0: f, 1: h
+    __shared__ double part[WG3];
+    const Consts3<double>& k = sd->kd;
+    const double scale = lat == 0 ? k.scale_f : k.scale_h;
+    const double qref = lat == 0 ? k.qref_f : 0.0;
+    const S* p = static_cast<const S*>(pop) + (int64_t)lat * 27 * vol + (int64_t)row * nx;
+    double s = 0.0;
+    for (int x = threadIdx.x; x < nx; x += WG3)
+        for (int q = 0; q < 27; ++q) s += wgt3<double>(q) * (double(p[(int64_t)q * vol + x]) / scale + qref);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = WG3 / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rows[lat * ny * nz + row] = part[0];
+}
+
+__global__ void k_inventory_final3(const double* rows, int n, double* out) {
+    __shared__ double part[WG3];
+    for (int lat = 0; lat < 2; ++lat) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n; i += WG3) s += rows[lat * n + i];
+        part[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = WG3 / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[lat] = part[0];
+        __syncthreads();
+    }
+}
+
+}  // namespace cmlb3

@@ -224,3 +224,96 @@ def random_fields(nx, ny, seed=0, flow="coupled", bc_y="walls", amp=0.05, **kw):
 
 def nodes(p) -> int:
     return int(p["nx"]) * int(p["ny"])
+
+
+# ---------------------------------------------------------------------------
+# Three-dimensional (D3Q27) inputs: the same analytic set-ups with a sphere
+# (fields [nz][ny][nx], x fastest)
+# ---------------------------------------------------------------------------
+
+def params3(**kw) -> dict:
+    p = params(**kw)
+    p.setdefault("nz", 16)
+    p.setdefault("F_ext_z", 0.0)
+    return p
+
+
+def drop_fields3(nx, ny, nz, xc, yc, zc, R, W, c_hat=None, phi_a=1.0, phi_b=0.0, y_offset=0.0):
+    """tanh sphere (Eq. CACEeq with zeta = R - |x - x_o|) and sech^2
+    surfactant band (Eq. ISSeq); node (i, j, k) sits at (i, j + y_offset, k).
+    ``c_hat``: callable of (cos of the polar angle from +x), constant, or None."""
+    x = np.arange(nx, dtype=np.float64)[None, None, :] - xc
+    y = np.arange(ny, dtype=np.float64)[None, :, None] + y_offset - yc
+    z = np.arange(nz, dtype=np.float64)[:, None, None] - zc
+    r = np.sqrt(x * x + y * y + z * z)
+    zeta = R - r
+    phi = 0.5 * (phi_a + phi_b) + 0.5 * (phi_a - phi_b) * np.tanh(2.0 * zeta / W)
+    if c_hat is None:
+        ch = np.zeros_like(phi)
+    elif callable(c_hat):
+        ch = c_hat(np.where(r > 0, x / np.where(r > 0, r, 1.0), 0.0))
+    else:
+        ch = np.full_like(phi, float(c_hat))
+    c = ch / np.cosh(2.0 * zeta / W) ** 2
+    return np.ascontiguousarray(phi), np.ascontiguousarray(c)
+
+
+def static_drop3(n=64, R=16.0, W=4.0, D_s=0.05, M_phi=0.1, center=None):
+    """Static sphere with c_hat = (1 - cos theta)/2 (theta from +x): the
+    l = 1 surface mode of Sec. 4.1 in 3D, decaying as exp(-2 D_s t/R^2)."""
+    p = params3(nx=n, ny=n, nz=n, bc_y="periodic", flow="none", W=W, D_s=D_s, M_phi=M_phi)
+    xc, yc, zc = center if center is not None else (n / 2, n / 2, n / 2)
+    phi, c = drop_fields3(n, n, n, xc, yc, zc, R, W, lambda ct: 0.5 * (1.0 - ct))
+    return p, dict(phi=phi, c=c)
+
+
+def _smooth_noise3(rng, nx, ny, nz, modes=4, periodic_y=True):
+    x = np.arange(nx, dtype=np.float64)[None, None, :]
+    y = np.arange(ny, dtype=np.float64)[None, :, None]
+    z = np.arange(nz, dtype=np.float64)[:, None, None]
+    out = np.zeros((nz, ny, nx))
+    ly = ny if periodic_y else 2 * ny
+    for _ in range(modes):
+        kx, ky, kz = (int(v) for v in rng.integers(1, 3, 3))
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        out += (np.cos(2 * np.pi * kx * x / nx + ph[0]) * np.cos(2 * np.pi * ky * y / ly + ph[1])
+                * np.cos(2 * np.pi * kz * z / nz + ph[2]))
+    return out / np.sqrt(modes)
+
+
+def random_fields3(nx, ny, nz, seed=0, flow="coupled", bc_y="walls", amp=0.05, **kw):
+    """Seeded smooth 3D test fields: an off-node sphere with an
+    angle-dependent surfactant load plus low-wavenumber perturbations of phi,
+    c, u and P."""
+    rng = np.random.default_rng(seed)
+    p = params3(nx=nx, ny=ny, nz=nz, bc_y=bc_y, flow=flow, **kw)
+    R = min(nx, ny, nz) / 3.0
+    y_off = 0.5 if bc_y == "walls" else 0.0
+    per = bc_y != "walls"
+    phi, c = drop_fields3(nx, ny, nz, nx / 2.0 + 0.3, ny / 2.0 - 0.2, nz / 2.0 + 0.17, R, p["W"],
+                          lambda ct: 0.2 + 0.1 * ct + 0.05 * ct * ct, y_offset=y_off)
+    phi = phi + amp * 0.1 * _smooth_noise3(rng, nx, ny, nz, periodic_y=per)
+    c = c * (1.0 + amp * _smooth_noise3(rng, nx, ny, nz, periodic_y=per))
+    u = [amp * 0.01 * _smooth_noise3(rng, nx, ny, nz, periodic_y=per) for _ in range(3)]
+    P = CS2 + amp * 1e-3 * _smooth_noise3(rng, nx, ny, nz, periodic_y=per)
+    return p, dict(phi=np.ascontiguousarray(phi), c=np.ascontiguousarray(c),
+                   ux=np.ascontiguousarray(u[0]), uy=np.ascontiguousarray(u[1]),
+                   uz=np.ascontiguousarray(u[2]), P=np.ascontiguousarray(P))
+
+
+def shear_drop3(nx=256, ny=128, nz=128, R=32.0, W=4.0, Ca=0.3, E=0.2, c0=0.3, Re=0.1, nu=0.1,
+                Pe_s=1.0, Pe_star=0.5, rho=1.0, omega_zeta=1.0, c_max=1.0):
+    """3D surfactant-laden drop in simple shear between walls at y = -1/2 and
+    ny - 1/2 moving at -+U0 along x, periodic in x and z: the Sec. 4.3
+    set-up with a sphere (parameters defined as in shear_drop)."""
+    H = float(ny)
+    gdot = Re * nu / (R * R)
+    U0 = gdot * H / 2.0
+    p = params3(nx=nx, ny=ny, nz=nz, bc_y="walls", flow="coupled", W=W,
+                M_phi=U0 * W / Pe_star, D_s=gdot * R * R / Pe_s, rho_a=rho, rho_b=rho,
+                nu_a=nu, nu_b=nu, omega_zeta=omega_zeta, sigma0=rho * nu * gdot * R / Ca,
+                beta=E, c_max=c_max, u_wall=U0)
+    phi, c = drop_fields3(nx, ny, nz, nx / 2.0, H / 2.0, nz / 2.0, R, W, c0, y_offset=0.5)
+    y = np.arange(ny, dtype=np.float64)[None, :, None] + 0.5
+    ux = np.ascontiguousarray(np.broadcast_to(U0 * (2.0 * y / H - 1.0), (nz, ny, nx)))
+    return p, dict(phi=phi, c=c, ux=ux, uy=np.zeros((nz, ny, nx)), uz=np.zeros((nz, ny, nx)))

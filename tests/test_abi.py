@@ -11,6 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "cmlb.h")
+HEADER3 = os.path.join(ROOT, "include", "cmlb3.h")
 
 
 @pytest.fixture(scope="module")
@@ -21,10 +22,10 @@ def lib():
     return cmlb.load()
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER, prefix="cmlb_"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cmlb_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_0-9]+)\s*\(", text)))
 
 
 def test_header_declares_the_binding_names():
@@ -32,13 +33,19 @@ def test_header_declares_the_binding_names():
     assert declared_functions() == sorted(cmlb.EXPORTS)
 
 
+def test_header3_declares_the_binding_names():
+    from paper_2504_09024_amd import cmlb
+    assert declared_functions(HEADER3, "cmlb3_") == sorted(cmlb.EXPORTS3)
+
+
 def test_library_exports_every_declared_symbol(lib):
-    for name in declared_functions():
+    names = declared_functions() + declared_functions(HEADER3, "cmlb3_")
+    for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", lib._name], capture_output=True,
                          text=True, check=True).stdout
-    exported = set(re.findall(r"\s(cmlb_\w+)$", out, flags=re.M))
-    assert set(declared_functions()) <= exported
+    exported = set(re.findall(r"\s(cmlb3?_\w+)$", out, flags=re.M))
+    assert set(names) <= exported
 
 
 def test_param_struct_layout_matches_c():
@@ -58,6 +65,49 @@ def test_param_struct_layout_matches_c():
     assert vals[0] == ctypes.sizeof(cmlb.SimParams)
     for f, off in zip(fields, vals[1:]):
         assert getattr(cmlb.SimParams, f).offset == off, f
+
+
+def test_param3_struct_layout_matches_c():
+    from paper_2504_09024_amd import cmlb
+    fields = [f for f, _ in cmlb.SimParams3._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER3}"', "int main(void){",
+           'printf("%zu\\n", sizeof(cmlb3_sim_params));']
+    src += [f'printf("%zu\\n", offsetof(cmlb3_sim_params, {f}));' for f in fields]
+    src += ["return 0;}"]
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write("\n".join(src))
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                               check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(cmlb.SimParams3)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(cmlb.SimParams3, f).offset == off, f
+
+
+def test_validation3_before_device(lib):
+    from paper_2504_09024_amd import cmlb
+    from paper_2504_09024_amd import workloads as W
+    good = dict(W.params(nx=32, ny=16), nz=8)
+
+    def create(plist, prec=0):
+        arr = (cmlb.SimParams3 * max(len(plist), 1))(*[cmlb.make_params3(p) for p in plist])
+        h = ctypes.c_void_p()
+        return lib.cmlb3_create(arr, len(plist), prec, None, ctypes.byref(h))
+
+    assert create([]) == cmlb.EINVAL
+    assert create([dict(good, nz=0)]) == cmlb.EINVAL
+    assert create([dict(good, ny=2)]) == cmlb.EINVAL
+    assert create([good], prec=5) == cmlb.EINVAL
+    assert create([good, dict(good, flow="coupled")]) == cmlb.EINVAL
+    assert create([dict(good, flow="coupled", omega_zeta=2.5)]) == cmlb.EUNSTABLE
+    # a lattice beyond the 32-bit buffer range
+    assert create([dict(good, nx=1024, ny=1024, nz=128)], prec=0) == cmlb.EINVAL
+    assert lib.cmlb3_step(None, 1) == cmlb.EINVAL
+    assert lib.cmlb3_step_count(None) == -1
+    assert lib.cmlb3_last_error(None) == b"null context"
+    lib.cmlb3_destroy(None)
 
 
 def _create(lib, plist, prec=0):

@@ -1,0 +1,192 @@
+"""GPU parity of the 3D (D3Q27) path against the FP64 3D oracle, through
+the C ABI of include/cmlb3.h.
+
+Tolerances (relative L2 per field at the final step): FP64 <= 1e-12,
+FP32 <= 1e-5 on phi, c, u, FP16 storage <= 1e-3.  Sizes span several
+64 x 4 x 2 collision tiles and 64 x 4-row moment tiles with ragged tails in
+x, y and z; the FP64 cases are checked to be well conditioned on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_09024_amd import workloads as W
+from parity_cases3 import CASES3
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 1e-3}
+CS2 = 1.0 / 3.0
+
+
+def ctx3(p, fl, prec, graph=True):
+    from paper_2504_09024_amd import cmlb
+    ps, fls = (p, fl) if isinstance(p, list) else ([p], [fl])
+    c = cmlb.Context3(ps, prec)
+    c.set_use_graph(graph)
+    for i, f in enumerate(fls):
+        c.init_fields(i, f["phi"], f["c"], f.get("ux"), f.get("uy"), f.get("uz"), f.get("P"))
+    return c
+
+
+def oracle3(oracle_mod, p, fl):
+    return oracle_mod.OracleSim3(oracle_mod.make_params3(**p), fl["phi"], fl["c"], fl.get("ux"),
+                                 fl.get("uy"), fl.get("uz"), fl.get("P"))
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def errors3(g, o, flow):
+    err = {"phi": rel(g["phi"], o["phi"]), "c": rel(g["c"], o["c"])}
+    if flow != "none":
+        u = lambda r: np.stack([r["ux"], r["uy"], r["uz"]])
+        err["u"] = rel(u(g), u(o))
+    if flow == "coupled":
+        err["P"] = rel(g["P"], o["P"])
+    return err
+
+
+@pytest.mark.parametrize("name", ["static3", "prescribed3", "coupled3"])
+def test_init_populations3(oracle_mod, gpu_lib, name):
+    build, _ = CASES3[name]
+    p, fl = build()
+    o = oracle3(oracle_mod, p, fl)
+    c = ctx3(p, fl, "fp64")
+    f, h, g = c.get_populations(0)
+    for a, b in ((f, o.f), (h, o.h)) + (((g, o.g),) if o.g is not None else ()):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+    c.close()
+
+
+PARITY3 = [("static3", "fp64"), ("static3", "fp32"), ("prescribed3", "fp64"),
+           ("prescribed3", "fp32"), ("coupled3", "fp64"), ("coupled3", "fp32"),
+           ("density3", "fp64"), ("shear3", "fp64"), ("shear3", "fp32"),
+           ("static3", "fp16"), ("shear3", "fp16")]
+
+
+@pytest.mark.parametrize("name,prec", PARITY3)
+def test_parity3(oracle_mod, gpu_lib, name, prec):
+    build, steps = CASES3[name]
+    p, fl = build()
+    o = oracle3(oracle_mod, p, fl)
+    c = ctx3(p, fl, prec)
+    c.step(steps)
+    g = c.read_fields(0)
+    assert o.run(steps) == 0
+    err = errors3(g, o.fields(), p["flow"])
+    print(name, prec, {k: f"{v:.2e}" for k, v in err.items()})
+    for k in ("phi", "c", "u"):
+        if k in err:
+            assert err[k] <= TOL[prec], (k, err[k])
+    if prec == "fp64" and "P" in err:
+        assert err["P"] <= TOL[prec]
+    c.close()
+
+
+def test_graph_matches_direct3(gpu_lib):
+    p, fl = CASES3["coupled3"][0]()
+    outs = []
+    for graph in (True, False):
+        c = ctx3(p, fl, "fp32", graph=graph)
+        for n in (35, 3):
+            c.step(n)
+        assert c.step_count == 38
+        outs.append(c.get_populations(0))
+        c.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_batched_matches_single3(gpu_lib):
+    cases = [CASES3["coupled3"][0](), W.random_fields3(40, 16, 9, seed=7, amp=1.0, sigma0=1e-3,
+                                                       beta=0.2, u_wall=1e-2, M_phi=0.04)]
+    c = ctx3([x[0] for x in cases], [x[1] for x in cases], "fp64")
+    c.step(30)
+    batched = [c.get_populations(i) for i in range(2)]
+    c.close()
+    for i, (p, fl) in enumerate(cases):
+        s = ctx3(p, fl, "fp64")
+        s.step(30)
+        for a, b in zip(batched[i], s.get_populations(0)):
+            assert np.array_equal(a, b)
+        s.close()
+
+
+def test_conservation3_fp64(gpu_lib):
+    p, fl = CASES3["coupled3"][0]()
+    c = ctx3(p, fl, "fp64")
+    s0 = c.inventory(0)
+    c.step(400)
+    s1 = c.inventory(0)
+    assert c.fault_flags(0) == 0
+    for a, b in zip(s1, s0):
+        assert abs(a - b) / abs(b) < 1e-13, (a, b)
+    c.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-6)])
+def test_c5_full_size_one_step(oracle_mod, gpu_lib, prec, tol):
+    """256 x 128 x 128 coupled shear drop (R = 32, Ca = 0.3, E = 0.2, c0 = 0.3,
+    Re = 0.1) in the benchmark's launch configuration: after 20 GPU steps,
+    one more step from the GPU's own populations through the oracle."""
+    p, fl = W.shear_drop3()
+    c = ctx3(p, fl, prec)
+    c.step(20)
+    f, h, g = c.get_populations(0)
+    o = oracle_mod.OracleSim3.from_populations(oracle_mod.make_params3(**p), f, h, g, t=20)
+    del f, h, g
+    c.step(1)
+    assert o.run(1) == 0
+    gf, gh, gg = c.get_populations(0)
+    for a, b in ((gf, o.f), (gh, o.h), (gg, o.g)):
+        d = np.abs(a - b).max() / np.abs(b).max()
+        print(prec, f"one-step max rel diff {d:.2e}")
+        assert d <= tol, d
+    c.close()
+
+
+def test_laplace_law_3d(gpu_lib):
+    """Clean static sphere (beta = 0, no surfactant): the pressure jump
+    settles at 2 sigma0/R (the 3D curvature and force normalisation)."""
+    n, R, sigma0 = 48, 12.0, 1e-3
+    phi, _ = W.drop_fields3(n, n, n, 24.3, 23.8, 24.1, R, 4.0)
+    p = W.params3(nx=n, ny=n, nz=n, bc_y="periodic", flow="coupled", sigma0=sigma0, beta=0.0,
+                  M_phi=0.05)
+    c = ctx3(p, dict(phi=phi, c=np.zeros_like(phi)), "fp64")
+    c.step(3000)
+    f = c.read_fields(0)
+    r = np.sqrt((np.arange(n)[None, None, :] - 24.3) ** 2 + (np.arange(n)[None, :, None] - 23.8) ** 2
+                + (np.arange(n)[:, None, None] - 24.1) ** 2)
+    dP = f["P"][r < R - 5].mean() - f["P"][r > R + 8].mean()
+    print(f"Laplace 3D: dP = {dP:.4e}, 2 sigma/R = {2 * sigma0 / R:.4e}")
+    assert abs(dP / (2 * sigma0 / R) - 1) < 0.05
+    c.close()
+
+
+def test_sphere_surface_diffusion_l1(gpu_lib):
+    """c_hat = (1 - cos theta)/2 on a static sphere: the l = 1 mode decays as
+    exp(-l(l+1) D_s t/R^2) = exp(-2 D_s t/R^2)."""
+    n, R, D = 64, 20.0, 0.1
+    p, fl = W.static_drop3(n=n, R=R, D_s=D, center=(32.3, 31.8, 32.1))
+    c = ctx3(p, fl, "fp64")
+    x = np.arange(n)[None, None, :] - 32.3
+    y = np.arange(n)[None, :, None] - 31.8
+    z = np.arange(n)[:, None, None] - 32.1
+    ct = x / np.sqrt(x * x + y * y + z * z)
+
+    def amp(cc):
+        return (cc * ct).sum() / cc.sum()
+
+    a0 = amp(c.read_fields(0)["c"])
+    steps = 1000
+    c.step(steps)
+    a1 = amp(c.read_fields(0)["c"])
+    measured = -math.log(a1 / a0)
+    expected = 2 * D * steps / R ** 2
+    print(f"sphere l=1: measured {measured:.4f} expected {expected:.4f}")
+    assert abs(measured / expected - 1) < 0.05
+    c.close()
