@@ -39,9 +39,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_node(prec, lattices=3):
-    """Every population read once and written once per step."""
-    return lattices * 9 * 2 * STORAGE_BYTES[prec]
+def algorithmic_bytes_per_node(prec, lattices=3, q=9):
+    """Every population read once and written once per step (q = 9 for
+    D2Q9, 27 for D3Q27)."""
+    return lattices * q * 2 * STORAGE_BYTES[prec]
 
 
 def kernel_hash():
@@ -68,6 +69,17 @@ def timed_run(ctx, steps, warmup, torch):
     wall = time.perf_counter() - t0
     ctx.synchronize()
     return start.elapsed_time(end) / 1e3, wall
+
+
+def make_ctx3(cmlb, sims, prec, stream, graph=True, shape=None):
+    ctx = cmlb.Context3([s[0] for s in sims], prec, stream=stream)
+    ctx.set_use_graph(graph)
+    if shape:
+        ctx.set_tile_shape(*shape)
+    for i, (_, fl) in enumerate(sims):
+        ctx.init_fields(i, fl["phi"], fl["c"], fl.get("ux"), fl.get("uy"), fl.get("uz"),
+                        fl.get("P"))
+    return ctx
 
 
 def make_ctx(cmlb, sims, prec, stream, tile_rows=0, graph=True, xcd_remap=True, group=-1,
@@ -182,7 +194,10 @@ def cpu_baseline(sims, target_s=12.0):
                       f"coupled, {dt:.1f} s, FP64, OpenMP over rows)"}
 
 
-WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2")
+WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2", "c5")
+# storage forms reported beside the headline: the batch, the single
+# 1024x512 drop and the 3D drop
+FORM_WORKLOADS = ("batched", "c3", "c5")
 
 
 def workload(W, name):
@@ -206,6 +221,10 @@ def workload(W, name):
         sims = [W.static_drop(n=512, R=128.0, D_s=d) for d in (0.05, 0.1, 0.2)]
         desc = ("three static drops (Sec. 4.1), 512x512 periodic, R=128, W=4, "
                 "D_s in {0.05, 0.1, 0.2}, phi and c lattices, one launch per step")
+    elif name == "c5":
+        sims = [W.shear_drop3()]
+        desc = ("3D (D3Q27) coupled surfactant-laden drop in shear, 256x128x128, R=32, Ca=0.3, "
+                "E=0.2, c0/c_max=0.3, Re=0.1, walls at +-U0; moments and collision launches")
     elif name == "e2":
         sims = [W.advected_drop()]
         desc = ("drop in a uniform flow (Sec. 4.2), 1024x512 periodic, R=128, D_s=0.1, "
@@ -219,6 +238,14 @@ def lattices_of(sims):
     return 3 if sims[0][0].get("flow") == "coupled" else 2
 
 
+def q_of(sims):
+    return 27 if "nz" in sims[0][0] else 9
+
+
+def nodes_of(sims):
+    return sum(p["nx"] * p["ny"] * p.get("nz", 1) for p, _ in sims)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +255,7 @@ def main():
     ap.add_argument("--workload", default="batched", choices=list(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-width", type=int, default=0, help="64 or 128 (with --tile-rows)")
+    ap.add_argument("--tile3", default="", help="3D collision tile ty,tz (e.g. 4,2)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-xcd-remap", action="store_true")
     ap.add_argument("--stores", default="auto", choices=["auto", "default", "nt"],
@@ -288,14 +316,19 @@ def main():
         return
 
     sims, desc = workload(W, args.workload)
-    nodes = sum(p["nx"] * p["ny"] for p, _ in sims)
+    dim3 = "nz" in sims[0][0]
+    nodes = nodes_of(sims)
     prec = args.precision
     log(f"[bench] workload {args.workload} ({len(sims)} sims, {nodes} nodes), {prec}, "
         f"warmup {args.warmup}, steps {args.steps}")
-    ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
-                   not args.no_xcd_remap, args.tile_group, args.stores, args.tile_width)
+    if dim3:
+        ctx = make_ctx3(cmlb, sims, prec, stream, not args.no_graph,
+                        tuple(int(v) for v in args.tile3.split(",")) if args.tile3 else None)
+    else:
+        ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
+                       not args.no_xcd_remap, args.tile_group, args.stores, args.tile_width)
     tuned = None
-    if not args.no_autotune and not args.tile_rows and args.stores == "auto":
+    if not dim3 and not args.no_autotune and not args.tile_rows and args.stores == "auto":
         tuned = ctx.autotune(20)
         log(f"[bench] autotuned launch: {tuned[0]}x{tuned[1]} tiles, {tuned[2]} stores")
     gpu_s, wall_s = timed_run(ctx, args.steps, args.warmup, torch)
@@ -304,7 +337,7 @@ def main():
     mlups = nodes * args.steps / gpu_s / 1e6
     ms_per_step = gpu_s * 1e3 / args.steps
     lat = lattices_of(sims)
-    bpl = algorithmic_bytes_per_node(prec, lat) * nodes
+    bpl = algorithmic_bytes_per_node(prec, lat, q_of(sims)) * nodes
     achieved = bpl / (gpu_s / args.steps) / 1e9
     log(f"[bench] {mlups:.0f} MLUPS, {ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s "
         f"({achieved / HBM_PEAK_GBS:.3f} of peak; wall {wall_s:.3f} s)")
@@ -312,22 +345,26 @@ def main():
     forms = {f"{args.workload}_{prec}": {"MLUPS": round(mlups, 1),
                                          "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}}
     if not args.no_forms:
-        for wl in ("batched", "c3"):
+        for wl in FORM_WORKLOADS:
             wsims, _ = workload(W, wl) if wl != args.workload else (sims, None)
-            wnodes = sum(p["nx"] * p["ny"] for p, _ in wsims)
+            wnodes = nodes_of(wsims)
             for fp in ("fp64", "fp32", "fp16"):
                 key = f"{wl}_{fp}"
                 if key in forms:
                     continue
-                c2 = make_ctx(cmlb, wsims, fp, stream)
-                k = 200 if wl == "batched" else 2000
+                if "nz" in wsims[0][0]:
+                    c2 = make_ctx3(cmlb, wsims, fp, stream)
+                else:
+                    c2 = make_ctx(cmlb, wsims, fp, stream)
+                k = {"batched": 200, "c3": 2000, "c5": 200}[wl]
                 s, _ = timed_run(c2, k, 20, torch)
                 c2.close()
-                bw = algorithmic_bytes_per_node(fp) * wnodes / (s / k) / 1e9
+                bw = (algorithmic_bytes_per_node(fp, lattices_of(wsims), q_of(wsims)) * wnodes
+                      / (s / k) / 1e9)
                 forms[key] = {"MLUPS": round(wnodes * k / s / 1e6, 1),
                               "hbm_frac": round(bw / HBM_PEAK_GBS, 4)}
                 log(f"[bench] form {key}: {forms[key]}")
-        for wl in ("batched", "c3"):
+        for wl in FORM_WORKLOADS:
             base = forms.get(f"{wl}_fp64", {}).get("MLUPS")
             for fp in ("fp64", "fp32", "fp16"):
                 key = f"{wl}_{fp}"
@@ -356,6 +393,7 @@ def main():
         "config": {
             "workload": desc,
             "sims": len(sims), "nodes": nodes, "storage": prec, "lattices": lat,
+            "velocities": q_of(sims),
             "graph": not args.no_graph, "tile_rows": args.tile_rows or "default",
             "tile_width": args.tile_width or "default",
             "xcd_remap": not args.no_xcd_remap,

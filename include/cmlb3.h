@@ -91,6 +91,13 @@ int cmlb3_fault_flags(cmlb3_ctx* ctx, int32_t sim, int32_t* flags);
 /* Block until the context's stream is idle; CMLB_ERANGE if a fault flag is set. */
 int cmlb3_synchronize(cmlb3_ctx* ctx);
 
+/* Collision tile shape: 64 x ty x tz nodes per workgroup (ty*tz waves).
+ * Accepted (ty, tz) pairs are listed by cmlb3_launch_options; (0, 0)
+ * restores the default (4, 2).  Results do not depend on it (bitwise). */
+int cmlb3_set_tile_shape(cmlb3_ctx* ctx, int32_t ty, int32_t tz);
+/* Writes up to cap/2 accepted (ty, tz) pairs into shapes[]; returns the count. */
+int cmlb3_launch_options(const cmlb3_ctx* ctx, int32_t* shapes, int32_t cap);
+
 /* Replay steps through HIP graphs (1, default) or launch directly (0).
  * Results do not depend on it. */
 int cmlb3_set_use_graph(cmlb3_ctx* ctx, int32_t on);

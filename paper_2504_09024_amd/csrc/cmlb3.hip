@@ -20,7 +20,13 @@ using namespace cmlb3;
 namespace {
 
 constexpr int GRAPH_STEPS3 = 16;  // steps per graph (even: the graph ends on its start parity)
-constexpr int CTY = 4, CTZ = 2;   // collision tile: 64 x CTY x CTZ nodes, CTY*CTZ waves
+// collision tiles 64 x ty x tz (ty*tz waves); the field read-out uses 64 x 2 x 2
+struct Shape3 {
+    int ty, tz;
+};
+const Shape3 SHAPES3[] = {{4, 2}, {3, 2}, {2, 2}};
+constexpr int N_SHAPES3 = sizeof(SHAPES3) / sizeof(Shape3);
+constexpr int FTY = 2, FTZ = 2;
 
 size_t sbytes(int prec) { return prec == CMLB_FP64 ? 8 : (prec == CMLB_FP32 ? 4 : 2); }
 double omega3(double coeff) { return 1.0 / (coeff * 3.0 + 0.5); }
@@ -89,7 +95,10 @@ struct cmlb3_ctx {
     SimDev3* d_sims = nullptr;
     int4* d_mtiles = nullptr;
     int4* d_ctiles = nullptr;
+    int4* d_ftiles = nullptr;
     int n_mtiles = 0, n_ctiles = 0;
+    int cty = 4, ctz = 2;           // collision tile shape
+    std::vector<int> ftile0, fntiles;
     int64_t* d_step = nullptr;
     int32_t* d_fault = nullptr;
     double* d_rows = nullptr;
@@ -142,6 +151,7 @@ void release3(cmlb3_ctx* c) {
     (void)hipFree(c->d_sims);
     (void)hipFree(c->d_mtiles);
     (void)hipFree(c->d_ctiles);
+    (void)hipFree(c->d_ftiles);
     (void)hipFree(c->d_step);
     (void)hipFree(c->d_fault);
     (void)hipFree(c->d_rows);
@@ -152,16 +162,26 @@ void release3(cmlb3_ctx* c) {
 // ---------------------------------------------------------------- kernels --
 using Fn3 = void (*)(StepArgs3);
 
-template <class S, class T, bool FIELDS, bool NTS>
-Fn3 pick_collide_t(int flow, int walls) {
+template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
+Fn3 pick_shape3(int ty, int tz) {
+    if constexpr (FIELDS) {
+        return k_collide3<S, T, FLOW, WALLS, FTY, FTZ, true, false>;
+    } else {
+        if (ty == 3) return k_collide3<S, T, FLOW, WALLS, 3, 2, false, false>;
+        if (ty == 2) return k_collide3<S, T, FLOW, WALLS, 2, 2, false, false>;
+        return k_collide3<S, T, FLOW, WALLS, 4, 2, false, false>;
+    }
+}
+template <class S, class T, bool FIELDS>
+Fn3 pick_collide_t(int flow, int walls, int ty, int tz) {
     if (flow == FLOW_NONE)
-        return walls ? k_collide3<S, T, FLOW_NONE, true, CTY, CTZ, FIELDS, NTS>
-                     : k_collide3<S, T, FLOW_NONE, false, CTY, CTZ, FIELDS, NTS>;
+        return walls ? pick_shape3<S, T, FLOW_NONE, true, FIELDS>(ty, tz)
+                     : pick_shape3<S, T, FLOW_NONE, false, FIELDS>(ty, tz);
     if (flow == FLOW_PRESCRIBED)
-        return walls ? k_collide3<S, T, FLOW_PRESCRIBED, true, CTY, CTZ, FIELDS, NTS>
-                     : k_collide3<S, T, FLOW_PRESCRIBED, false, CTY, CTZ, FIELDS, NTS>;
-    return walls ? k_collide3<S, T, FLOW_COUPLED, true, CTY, CTZ, FIELDS, NTS>
-                 : k_collide3<S, T, FLOW_COUPLED, false, CTY, CTZ, FIELDS, NTS>;
+        return walls ? pick_shape3<S, T, FLOW_PRESCRIBED, true, FIELDS>(ty, tz)
+                     : pick_shape3<S, T, FLOW_PRESCRIBED, false, FIELDS>(ty, tz);
+    return walls ? pick_shape3<S, T, FLOW_COUPLED, true, FIELDS>(ty, tz)
+                 : pick_shape3<S, T, FLOW_COUPLED, false, FIELDS>(ty, tz);
 }
 template <class S, class T>
 Fn3 pick_moments_t(int flow, int walls) {
@@ -170,14 +190,15 @@ Fn3 pick_moments_t(int flow, int walls) {
     return walls ? k_moments3<S, T, FLOW_NONE, true> : k_moments3<S, T, FLOW_NONE, false>;
 }
 Fn3 pick_collide(const cmlb3_ctx* c, bool fields) {
+    const int ty = c->cty, tz = c->ctz;
     if (c->prec == CMLB_FP64)
-        return fields ? pick_collide_t<double, double, true, false>(c->flow, c->walls)
-                      : pick_collide_t<double, double, false, false>(c->flow, c->walls);
+        return fields ? pick_collide_t<double, double, true>(c->flow, c->walls, ty, tz)
+                      : pick_collide_t<double, double, false>(c->flow, c->walls, ty, tz);
     if (c->prec == CMLB_FP32)
-        return fields ? pick_collide_t<float, float, true, false>(c->flow, c->walls)
-                      : pick_collide_t<float, float, false, false>(c->flow, c->walls);
-    return fields ? pick_collide_t<_Float16, float, true, false>(c->flow, c->walls)
-                  : pick_collide_t<_Float16, float, false, false>(c->flow, c->walls);
+        return fields ? pick_collide_t<float, float, true>(c->flow, c->walls, ty, tz)
+                      : pick_collide_t<float, float, false>(c->flow, c->walls, ty, tz);
+    return fields ? pick_collide_t<_Float16, float, true>(c->flow, c->walls, ty, tz)
+                  : pick_collide_t<_Float16, float, false>(c->flow, c->walls, ty, tz);
 }
 Fn3 pick_moments(const cmlb3_ctx* c) {
     if (c->prec == CMLB_FP64) return pick_moments_t<double, double>(c->flow, c->walls);
@@ -210,8 +231,8 @@ int launch_pair(cmlb3_ctx* c, int parity) {
     hipLaunchKernelGGL(pick_moments(c), dim3(grid_of(c->n_mtiles)), dim3(WG3), 0, c->stream, am);
     HIP3(c, hipGetLastError());
     StepArgs3 ac = args3(c, parity, false);
-    hipLaunchKernelGGL(pick_collide(c, false), dim3(grid_of(c->n_ctiles)), dim3(CTY * CTZ * 64), 0,
-                       c->stream, ac);
+    hipLaunchKernelGGL(pick_collide(c, false), dim3(grid_of(c->n_ctiles)), dim3(c->cty * c->ctz * 64),
+                       0, c->stream, ac);
     HIP3(c, hipGetLastError());
     return CMLB_OK;
 }
@@ -228,7 +249,7 @@ int build_graph3(cmlb3_ctx* c, int p) {
             memset(&np, 0, sizeof(np));
             np.func = reinterpret_cast<void*>(mom ? pick_moments(c) : pick_collide(c, false));
             np.gridDim = dim3(grid_of(mom ? c->n_mtiles : c->n_ctiles));
-            np.blockDim = dim3(mom ? WG3 : CTY * CTZ * 64);
+            np.blockDim = dim3(mom ? WG3 : c->cty * c->ctz * 64);
             np.kernelParams = kargs;
             hipGraphNode_t node;
             HIP3(c, hipGraphAddKernelNode(&node, c->graph[p], prev ? &prev : nullptr, prev ? 1 : 0,
@@ -237,6 +258,32 @@ int build_graph3(cmlb3_ctx* c, int p) {
         }
     }
     HIP3(c, hipGraphInstantiate(&c->gexec[p], c->graph[p], nullptr, nullptr, 0));
+    return CMLB_OK;
+}
+
+// collision tiles 64 x ty x tz of every simulation (z-major, then y, then x)
+std::vector<int4> collide_tiles(const std::vector<cmlb3_sim_params>& ps, int ty, int tz,
+                                std::vector<int>* first, std::vector<int>* count) {
+    std::vector<int4> ct;
+    for (int s = 0; s < (int)ps.size(); ++s) {
+        const cmlb3_sim_params& p = ps[s];
+        if (first) first->push_back((int)ct.size());
+        for (int z0 = 0; z0 < p.nz; z0 += tz)
+            for (int y0 = 0; y0 < p.ny; y0 += ty)
+                for (int x0 = 0; x0 < p.nx; x0 += TXW) ct.push_back(make_int4(s, x0, y0, z0));
+        if (count) count->push_back((int)ct.size() - first->back());
+    }
+    return ct;
+}
+
+int build_ctiles3(cmlb3_ctx* c) {
+    std::vector<int4> ct = collide_tiles(c->params, c->cty, c->ctz, nullptr, nullptr);
+    if (c->d_ctiles) (void)hipFree(c->d_ctiles);
+    c->d_ctiles = nullptr;
+    c->n_ctiles = (int)ct.size();
+    HIP3(c, hipMalloc(&c->d_ctiles, sizeof(int4) * ct.size()));
+    HIP3(c, hipMemcpy(c->d_ctiles, ct.data(), sizeof(int4) * ct.size(), hipMemcpyHostToDevice));
+    drop_graphs3(c);
     return CMLB_OK;
 }
 
@@ -283,7 +330,7 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
     const int nlat = flow == CMLB_FLOW_COUPLED ? 3 : 2;
     const size_t sb = sbytes(precision);
     std::vector<SimDev3> sims(n_sims);
-    std::vector<int4> mt, ct;
+    std::vector<int4> mt;
     int64_t off = 0, moff = 0, uoff = 0, max_vol = 0, max_rows = 0, nodes = 0;
     for (int s = 0; s < n_sims; ++s) {
         const cmlb3_sim_params& p = params[s];
@@ -331,15 +378,10 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
         sd.vel_period_T = p.vel_period_T;
         fill3(sd.kd, p, d, walls);
         fill3(sd.kf, p, d, walls);
-        // tile tables: moments 64 x MT_ROWS rows; collision 64 x CTY x CTZ
+        // moments tiles: 64 x MT_ROWS (y, z) rows
         const int rows = p.ny * p.nz;
         for (int r0 = 0; r0 < rows; r0 += MT_ROWS)
             for (int x0 = 0; x0 < p.nx; x0 += TXW) mt.push_back(make_int4(s, x0, r0, 0));
-        sd.tile0 = (int)ct.size();
-        for (int z0 = 0; z0 < p.nz; z0 += CTZ)
-            for (int y0 = 0; y0 < p.ny; y0 += CTY)
-                for (int x0 = 0; x0 < p.nx; x0 += TXW) ct.push_back(make_int4(s, x0, y0, z0));
-        sd.ntiles = (int)ct.size() - sd.tile0;
         sims[s] = sd;
         off += (int64_t)nlat * 27 * vol;
         moff += (int64_t)NMOM * vol;
@@ -364,6 +406,8 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
     c->max_vol = max_vol;
     c->max_rows = max_rows;
     c->n_mtiles = (int)mt.size();
+    std::vector<int4> ct = collide_tiles(c->params, c->cty, c->ctz, nullptr, nullptr);
+    std::vector<int4> ft = collide_tiles(c->params, FTY, FTZ, &c->ftile0, &c->fntiles);
     c->n_ctiles = (int)ct.size();
     auto bail = [&](int code) {
         release3(c);
@@ -386,6 +430,7 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
     if (hipMalloc(&c->d_sims, sizeof(SimDev3) * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_mtiles, sizeof(int4) * mt.size()) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_ctiles, sizeof(int4) * ct.size()) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_ftiles, sizeof(int4) * ft.size()) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_step, sizeof(int64_t) * 2) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_fault, sizeof(int32_t) * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_rows, sizeof(double) * 2 * max_rows) != hipSuccess)
@@ -401,6 +446,8 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
         hipMemcpy(c->d_mtiles, mt.data(), sizeof(int4) * mt.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemcpy(c->d_ctiles, ct.data(), sizeof(int4) * ct.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(c->d_ftiles, ft.data(), sizeof(int4) * ft.size(), hipMemcpyHostToDevice) !=
             hipSuccess)
         return bail(CMLB_EDEVICE);
     *out = c;
@@ -507,11 +554,12 @@ int cmlb3_read_fields(cmlb3_ctx* c, int32_t sim, double* phi, double* cc, double
         StepArgs3 a = args3(c, c->cur, false);
         a.dst = nullptr;
         a.step_out = nullptr;
-        a.tile_base = d.tile0;
-        a.ntiles = d.ntiles;
+        a.tiles = c->d_ftiles;
+        a.tile_base = c->ftile0[sim];
+        a.ntiles = c->fntiles[sim];
         a.xcd_remap = 0;
         a.fields_out = stage;
-        hipLaunchKernelGGL(pick_collide(c, true), dim3(d.ntiles), dim3(CTY * CTZ * 64), 0,
+        hipLaunchKernelGGL(pick_collide(c, true), dim3(c->fntiles[sim]), dim3(FTY * FTZ * 64), 0,
                            c->stream, a);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
             rc = fail3(c, CMLB_EDEVICE, "field kernel failed");
@@ -621,6 +669,30 @@ int cmlb3_fault_flags(cmlb3_ctx* c, int32_t sim, int32_t* flags) {
 int cmlb3_synchronize(cmlb3_ctx* c) {
     if (!c) return CMLB_EINVAL;
     return sync_check3(c);
+}
+
+int cmlb3_set_tile_shape(cmlb3_ctx* c, int32_t ty, int32_t tz) {
+    if (!c) return CMLB_EINVAL;
+    if (ty == 0 && tz == 0) {
+        ty = 4;
+        tz = 2;
+    }
+    bool ok = false;
+    for (int i = 0; i < N_SHAPES3; ++i) ok |= SHAPES3[i].ty == ty && SHAPES3[i].tz == tz;
+    if (!ok) return fail3(c, CMLB_EINVAL, "collision tile 64x%dx%d not supported", ty, tz);
+    HIP3(c, hipStreamSynchronize(c->stream));
+    c->cty = ty;
+    c->ctz = tz;
+    return build_ctiles3(c);
+}
+
+int cmlb3_launch_options(const cmlb3_ctx* c, int32_t* shapes, int32_t cap) {
+    if (!c || (!shapes && cap > 0)) return CMLB_EINVAL;
+    for (int i = 0; i < N_SHAPES3 && 2 * i + 1 < cap; ++i) {
+        shapes[2 * i] = SHAPES3[i].ty;
+        shapes[2 * i + 1] = SHAPES3[i].tz;
+    }
+    return N_SHAPES3;
 }
 
 int cmlb3_set_use_graph(cmlb3_ctx* c, int32_t on) {

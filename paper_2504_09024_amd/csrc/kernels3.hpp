@@ -93,9 +93,7 @@ struct Consts3 {
 
 struct SimDev3 {
     int32_t nx, ny, nz;
-    int32_t tile0, ntiles;
     int32_t uniform_rho, uniform_nu;
-    int32_t pad_;
     int64_t off;         // element offset of this sim's populations (3 x 27 planes)
     int64_t moff;        // element offset of its moments (18 planes)
     int64_t uoff;        // element offset of its prescribed velocity shapes (3 planes)
@@ -406,8 +404,11 @@ __device__ __forceinline__ void flow_dev27(const T eta2[6], T dP, T rho, T ux, T
 
 // Isotropic D3Q27 gradient from an LDS box of row pitch PX and plane pitch
 // PXY: d_i = (1/cs2) sum_a w_a e_ai F(x + e_a).
+// No FP contraction in the stencils: a value computed at a node must carry
+// the same bits whichever tile shape (kernel instance) computes it.
 template <class T, int PX, int PXY>
 __device__ __forceinline__ void lds_grad3(const T* L, int idx, T& gx, T& gy, T& gz) {
+#pragma clang fp contract(off)
     T sx = T(0), sy = T(0), sz = T(0);
 #pragma unroll
     for (int a = 1; a < 27; ++a) {
@@ -420,6 +421,37 @@ __device__ __forceinline__ void lds_grad3(const T* L, int idx, T& gx, T& gy, T& 
     gx = T(3) * sx;
     gy = T(3) * sy;
     gz = T(3) * sz;
+}
+
+// n = grad phi/(|grad phi| + eps), contraction off like the stencils
+template <class T, int PX, int PXY>
+__device__ __forceinline__ void unit_normal3(const T* L, int idx, T n[3]) {
+#pragma clang fp contract(off)
+    T gx, gy, gz;
+    lds_grad3<T, PX, PXY>(L, idx, gx, gy, gz);
+    const T inv = rcp_(sqrt_(gx * gx + gy * gy + gz * gz) + T(NORMAL_EPS3));
+    n[0] = gx * inv;
+    n[1] = gy * inv;
+    n[2] = gz * inv;
+}
+
+// Divergence of a vector field stored as three LDS planes (pitch NP apart)
+// with the same stencil: (1/cs2) sum_a w_a e_a . V(x + e_a).
+template <class T, int PX, int PXY, int NP>
+__device__ __forceinline__ T lds_div3(const T* V, int idx) {
+#pragma clang fp contract(off)
+    T s = T(0);
+#pragma unroll
+    for (int a = 1; a < 27; ++a) {
+        const int ex = EXd(a), ey = EYd(a), ez = EZd(a);
+        const int j = idx + ex + ey * PX + ez * PXY;
+        T d = T(0);
+        if (ex) d += ex > 0 ? V[j] : -V[j];
+        if (ey) d += ey > 0 ? V[NP + j] : -V[NP + j];
+        if (ez) d += ez > 0 ? V[2 * NP + j] : -V[2 * NP + j];
+        s += wgt3<T>(a) * d;
+    }
+    return T(3) * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -476,12 +508,11 @@ __global__ __launch_bounds__(TY* TZ * 64, (Occ3<T, TY * TZ>::waves_per_eu)) void
     if constexpr (CPL) {
         for (int i = tid; i < QX * QY * QZ; i += NT) {
             const int qz = i / (QX * QY), rem = i - qz * QX * QY, qy = rem / QX, qx = rem - qy * QX;
-            T gx, gy, gz;
-            lds_grad3<T, PX, PX * PY>(phiL, ((qz + 1) * PY + qy + 1) * PX + qx + 1, gx, gy, gz);
-            const T inv = rcp_(sqrt_(gx * gx + gy * gy + gz * gz) + T(NORMAL_EPS3));
-            nL[i] = gx * inv;
-            nL[QX * QY * QZ + i] = gy * inv;
-            nL[2 * QX * QY * QZ + i] = gz * inv;
+            T n3[3];
+            unit_normal3<T, PX, PX * PY>(phiL, ((qz + 1) * PY + qy + 1) * PX + qx + 1, n3);
+            nL[i] = n3[0];
+            nL[QX * QY * QZ + i] = n3[1];
+            nL[2 * QX * QY * QZ + i] = n3[2];
         }
         __syncthreads();
     }
@@ -505,10 +536,11 @@ __global__ __launch_bounds__(TY* TZ * 64, (Occ3<T, TY * TZ>::waves_per_eu)) void
         nyv = nL[QX * QY * QZ + qidx];
         nzv = nL[2 * QX * QY * QZ + qidx];
     } else {
-        const T inv = rcp_(sqrt_(gm2) + T(NORMAL_EPS3));
-        nxv = gpx * inv;
-        nyv = gpy * inv;
-        nzv = gpz * inv;
+        T n3[3];
+        unit_normal3<T, PX, PX * PY>(phiL, pidx, n3);
+        nxv = n3[0];
+        nyv = n3[1];
+        nzv = n3[2];
     }
     const T theta = k.theta_k * (k.phi_a - phi) * (phi - k.phi_b) * k.inv_dphi;
     const T theta_c = k.thetac_k * c * (k.phim - phi) * k.inv_dphi;
@@ -516,13 +548,11 @@ __global__ __launch_bounds__(TY* TZ * 64, (Occ3<T, TY * TZ>::waves_per_eu)) void
     T fp[3] = {T(0), T(0), T(0)}, ft[3] = {T(0), T(0), T(0)}, gam = T(0);
     int fault = 0;
     if constexpr (CPL) {
-        T dn[9], gc[3], gq[3];
-        lds_grad3<T, QX, QX * QY>(nL, qidx, dn[0], dn[1], dn[2]);
-        lds_grad3<T, QX, QX * QY>(nL + QX * QY * QZ, qidx, dn[3], dn[4], dn[5]);
-        lds_grad3<T, QX, QX * QY>(nL + 2 * QX * QY * QZ, qidx, dn[6], dn[7], dn[8]);
+        T gc[3], gq[3];
+        // curvature: divergence of the unit normal, same stencil
+        const T curv = lds_div3<T, QX, QX * QY, QX * QY * QZ>(nL, qidx);
         lds_grad3<T, QX, QX * QY>(cL, qidx, gc[0], gc[1], gc[2]);
         lds_grad3<T, QX, QX * QY>(pL, qidx, gq[0], gq[1], gq[2]);
-        const T curv = dn[0] + dn[4] + dn[8];
         const T lam = (phi - k.phi_b) * k.inv_dphi;
         rho = sd->uniform_rho ? k.rho_b : k.rho_b + lam * k.drho;
         const T inv_rho = sd->uniform_rho ? k.inv_rho_b : rcp_(rho);
