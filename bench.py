@@ -71,9 +71,10 @@ def timed_run(ctx, steps, warmup, torch):
     return start.elapsed_time(end) / 1e3, wall
 
 
-def make_ctx3(cmlb, sims, prec, stream, graph=True, shape=None):
+def make_ctx3(cmlb, sims, prec, stream, graph=True, shape=None, stores="auto"):
     ctx = cmlb.Context3([s[0] for s in sims], prec, stream=stream)
     ctx.set_use_graph(graph)
+    ctx.set_store_policy(stores)
     if shape:
         ctx.set_tile_shape(*shape)
     for i, (_, fl) in enumerate(sims):
@@ -255,7 +256,7 @@ def main():
     ap.add_argument("--workload", default="batched", choices=list(WORKLOADS))
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--tile-width", type=int, default=0, help="64 or 128 (with --tile-rows)")
-    ap.add_argument("--tile3", default="", help="3D collision tile ty,tz (e.g. 4,2)")
+    ap.add_argument("--tile3", default="", help="3D collision column ty,zs (e.g. 4,16)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-xcd-remap", action="store_true")
     ap.add_argument("--stores", default="auto", choices=["auto", "default", "nt"],
@@ -323,7 +324,8 @@ def main():
         f"warmup {args.warmup}, steps {args.steps}")
     if dim3:
         ctx = make_ctx3(cmlb, sims, prec, stream, not args.no_graph,
-                        tuple(int(v) for v in args.tile3.split(",")) if args.tile3 else None)
+                        tuple(int(v) for v in args.tile3.split(",")) if args.tile3 else None,
+                        args.stores)
     else:
         ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
                        not args.no_xcd_remap, args.tile_group, args.stores, args.tile_width)

@@ -162,7 +162,7 @@ int cmlb_synchronize(cmlb_ctx* ctx);
 /* Launch configuration of the step kernel: the workgroup tile is width x
  * rows nodes (width 64: one wavefront across x; 128: two).  Accepted pairs
  * are listed by cmlb_launch_options; (0, 0) restores the default.  Results
- * in FP64 do not depend on it (bitwise).  cmlb_set_tile_rows(ctx, r) is
+ * do not depend on it (bitwise).  cmlb_set_tile_rows(ctx, r) is
  * cmlb_set_tile_shape(ctx, 64, r) (r = 0: the default). */
 int cmlb_set_tile_shape(cmlb_ctx* ctx, int32_t width, int32_t rows);
 int cmlb_set_tile_rows(cmlb_ctx* ctx, int32_t rows);

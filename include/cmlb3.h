@@ -91,12 +91,20 @@ int cmlb3_fault_flags(cmlb3_ctx* ctx, int32_t sim, int32_t* flags);
 /* Block until the context's stream is idle; CMLB_ERANGE if a fault flag is set. */
 int cmlb3_synchronize(cmlb3_ctx* ctx);
 
-/* Collision tile shape: 64 x ty x tz nodes per workgroup (ty*tz waves).
- * Accepted (ty, tz) pairs are listed by cmlb3_launch_options; (0, 0)
- * restores the default (4, 2).  Results do not depend on it (bitwise). */
-int cmlb3_set_tile_shape(cmlb3_ctx* ctx, int32_t ty, int32_t tz);
-/* Writes up to cap/2 accepted (ty, tz) pairs into shapes[]; returns the count. */
+/* Collision launch shape: columns of 64 x ty nodes (ty waves per
+ * workgroup), each marching through zs consecutive z planes.  Accepted
+ * (ty, zs) pairs are listed by cmlb3_launch_options; (0, 0) restores the
+ * default ((8, 16) with FP32 storage, (4, 8) with FP16 and FP64).  Results
+ * do not depend on it (bitwise). */
+int cmlb3_set_tile_shape(cmlb3_ctx* ctx, int32_t ty, int32_t zs);
+/* Writes up to cap/2 accepted (ty, zs) pairs into shapes[]; returns the count. */
 int cmlb3_launch_options(const cmlb3_ctx* ctx, int32_t* shapes, int32_t cap);
+
+/* Cache policy of the collision kernel's population stores, as for
+ * cmlb_set_store_policy: 0 (default) non-temporal when the two population
+ * buffers together exceed 256 MiB, 1 default stores, 2 non-temporal.
+ * Results do not depend on it (bitwise). */
+int cmlb3_set_store_policy(cmlb3_ctx* ctx, int32_t policy);
 
 /* Replay steps through HIP graphs (1, default) or launch directly (0).
  * Results do not depend on it. */

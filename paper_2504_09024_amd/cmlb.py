@@ -50,7 +50,8 @@ EXPORTS = (
 EXPORTS3 = (
     "cmlb3_create", "cmlb3_init_fields", "cmlb3_step", "cmlb3_read_fields", "cmlb3_inventory",
     "cmlb3_get_populations", "cmlb3_set_populations", "cmlb3_fault_flags", "cmlb3_synchronize",
-    "cmlb3_set_use_graph", "cmlb3_set_tile_shape", "cmlb3_launch_options", "cmlb3_step_count",
+    "cmlb3_set_use_graph", "cmlb3_set_tile_shape", "cmlb3_launch_options",
+    "cmlb3_set_store_policy", "cmlb3_step_count",
     "cmlb3_last_error", "cmlb3_destroy",
 )
 
@@ -133,6 +134,7 @@ def load(path: str = LIB_PATH):
     L.cmlb3_synchronize.argtypes = [vp]
     L.cmlb3_set_use_graph.argtypes = [vp, ctypes.c_int32]
     L.cmlb3_set_tile_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.cmlb3_set_store_policy.argtypes = [vp, ctypes.c_int32]
     L.cmlb3_launch_options.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
     L.cmlb3_step_count.argtypes = [vp]
     L.cmlb3_step_count.restype = ctypes.c_int64
@@ -419,8 +421,16 @@ class Context3:
     def set_use_graph(self, on):
         self._check(self.L.cmlb3_set_use_graph(self.h, 1 if on else 0), "cmlb3_set_use_graph")
 
-    def set_tile_shape(self, ty, tz):
-        self._check(self.L.cmlb3_set_tile_shape(self.h, int(ty), int(tz)), "cmlb3_set_tile_shape")
+    def set_store_policy(self, policy):
+        """0 auto, 1 default stores, 2 non-temporal stores (or "auto",
+        "default", "nt")."""
+        if isinstance(policy, str):
+            policy = {"auto": 0, "default": 1, "nt": 2}[policy]
+        self._check(self.L.cmlb3_set_store_policy(self.h, int(policy)), "cmlb3_set_store_policy")
+
+    def set_tile_shape(self, ty, zs):
+        """Collision columns of 64 x ty nodes marching through zs planes."""
+        self._check(self.L.cmlb3_set_tile_shape(self.h, int(ty), int(zs)), "cmlb3_set_tile_shape")
 
     def launch_options(self):
         buf = (ctypes.c_int32 * 32)()

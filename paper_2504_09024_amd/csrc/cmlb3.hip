@@ -20,13 +20,18 @@ using namespace cmlb3;
 namespace {
 
 constexpr int GRAPH_STEPS3 = 16;  // steps per graph (even: the graph ends on its start parity)
-// collision tiles 64 x ty x tz (ty*tz waves); the field read-out uses 64 x 2 x 2
+// collision columns 64 x ty nodes (ty waves) marching through zs planes;
+// the field read-out uses 64 x 4 columns of 8 planes
 struct Shape3 {
-    int ty, tz;
+    int ty, zs;
 };
-const Shape3 SHAPES3[] = {{4, 2}, {3, 2}, {2, 2}};
+const Shape3 SHAPES3[] = {{4, 16}, {4, 8}, {8, 16}, {8, 8}, {4, 4}};
 constexpr int N_SHAPES3 = sizeof(SHAPES3) / sizeof(Shape3);
-constexpr int FTY = 2, FTZ = 2;
+constexpr int FTY = 4, FZS = 8;
+// fastest measured on the 256 x 128 x 128 coupled drop: FP32 64 x 8 columns
+// of 16 planes; FP16 and FP64 64 x 4 columns of 8 planes (FP64 at 64 x 8
+// would spill registers to memory)
+Shape3 default_shape3(int prec) { return prec == CMLB_FP32 ? Shape3{8, 16} : Shape3{4, 8}; }
 
 size_t sbytes(int prec) { return prec == CMLB_FP64 ? 8 : (prec == CMLB_FP32 ? 4 : 2); }
 double omega3(double coeff) { return 1.0 / (coeff * 3.0 + 0.5); }
@@ -97,7 +102,9 @@ struct cmlb3_ctx {
     int4* d_ctiles = nullptr;
     int4* d_ftiles = nullptr;
     int n_mtiles = 0, n_ctiles = 0;
-    int cty = 4, ctz = 2;           // collision tile shape
+    int cty = 4, czs = 16;          // collision column shape
+    int store_policy = 0;           // 0 auto, 1 default stores, 2 non-temporal stores
+    int64_t pop_bytes = 0;
     std::vector<int> ftile0, fntiles;
     int64_t* d_step = nullptr;
     int32_t* d_fault = nullptr;
@@ -163,25 +170,27 @@ void release3(cmlb3_ctx* c) {
 using Fn3 = void (*)(StepArgs3);
 
 template <class S, class T, int FLOW, bool WALLS, bool FIELDS>
-Fn3 pick_shape3(int ty, int tz) {
+Fn3 pick_shape3(int ty, bool nt) {
     if constexpr (FIELDS) {
-        return k_collide3<S, T, FLOW, WALLS, FTY, FTZ, true, false>;
+        return k_collide3<S, T, FLOW, WALLS, FTY, true, false>;
     } else {
-        if (ty == 3) return k_collide3<S, T, FLOW, WALLS, 3, 2, false, false>;
-        if (ty == 2) return k_collide3<S, T, FLOW, WALLS, 2, 2, false, false>;
-        return k_collide3<S, T, FLOW, WALLS, 4, 2, false, false>;
+        if (ty == 8)
+            return nt ? k_collide3<S, T, FLOW, WALLS, 8, false, true>
+                      : k_collide3<S, T, FLOW, WALLS, 8, false, false>;
+        return nt ? k_collide3<S, T, FLOW, WALLS, 4, false, true>
+                  : k_collide3<S, T, FLOW, WALLS, 4, false, false>;
     }
 }
 template <class S, class T, bool FIELDS>
-Fn3 pick_collide_t(int flow, int walls, int ty, int tz) {
+Fn3 pick_collide_t(int flow, int walls, int ty, bool nt) {
     if (flow == FLOW_NONE)
-        return walls ? pick_shape3<S, T, FLOW_NONE, true, FIELDS>(ty, tz)
-                     : pick_shape3<S, T, FLOW_NONE, false, FIELDS>(ty, tz);
+        return walls ? pick_shape3<S, T, FLOW_NONE, true, FIELDS>(ty, nt)
+                     : pick_shape3<S, T, FLOW_NONE, false, FIELDS>(ty, nt);
     if (flow == FLOW_PRESCRIBED)
-        return walls ? pick_shape3<S, T, FLOW_PRESCRIBED, true, FIELDS>(ty, tz)
-                     : pick_shape3<S, T, FLOW_PRESCRIBED, false, FIELDS>(ty, tz);
-    return walls ? pick_shape3<S, T, FLOW_COUPLED, true, FIELDS>(ty, tz)
-                 : pick_shape3<S, T, FLOW_COUPLED, false, FIELDS>(ty, tz);
+        return walls ? pick_shape3<S, T, FLOW_PRESCRIBED, true, FIELDS>(ty, nt)
+                     : pick_shape3<S, T, FLOW_PRESCRIBED, false, FIELDS>(ty, nt);
+    return walls ? pick_shape3<S, T, FLOW_COUPLED, true, FIELDS>(ty, nt)
+                 : pick_shape3<S, T, FLOW_COUPLED, false, FIELDS>(ty, nt);
 }
 template <class S, class T>
 Fn3 pick_moments_t(int flow, int walls) {
@@ -189,16 +198,27 @@ Fn3 pick_moments_t(int flow, int walls) {
         return walls ? k_moments3<S, T, FLOW_COUPLED, true> : k_moments3<S, T, FLOW_COUPLED, false>;
     return walls ? k_moments3<S, T, FLOW_NONE, true> : k_moments3<S, T, FLOW_NONE, false>;
 }
+// non-temporal population stores when the two population buffers exceed the
+// last-level cache (256 MiB Infinity Cache on MI355X): the write stream then
+// does not evict lines that neighbouring columns still read
+constexpr int64_t LLC_BYTES3 = int64_t(256) << 20;
+bool stores_nt3(const cmlb3_ctx* c) {
+    if (c->store_policy == 1) return false;
+    if (c->store_policy == 2) return true;
+    return 2 * c->pop_bytes > LLC_BYTES3;
+}
+
 Fn3 pick_collide(const cmlb3_ctx* c, bool fields) {
-    const int ty = c->cty, tz = c->ctz;
+    const int ty = c->cty;
+    const bool nt = stores_nt3(c);
     if (c->prec == CMLB_FP64)
-        return fields ? pick_collide_t<double, double, true>(c->flow, c->walls, ty, tz)
-                      : pick_collide_t<double, double, false>(c->flow, c->walls, ty, tz);
+        return fields ? pick_collide_t<double, double, true>(c->flow, c->walls, ty, nt)
+                      : pick_collide_t<double, double, false>(c->flow, c->walls, ty, nt);
     if (c->prec == CMLB_FP32)
-        return fields ? pick_collide_t<float, float, true>(c->flow, c->walls, ty, tz)
-                      : pick_collide_t<float, float, false>(c->flow, c->walls, ty, tz);
-    return fields ? pick_collide_t<_Float16, float, true>(c->flow, c->walls, ty, tz)
-                  : pick_collide_t<_Float16, float, false>(c->flow, c->walls, ty, tz);
+        return fields ? pick_collide_t<float, float, true>(c->flow, c->walls, ty, nt)
+                      : pick_collide_t<float, float, false>(c->flow, c->walls, ty, nt);
+    return fields ? pick_collide_t<_Float16, float, true>(c->flow, c->walls, ty, nt)
+                  : pick_collide_t<_Float16, float, false>(c->flow, c->walls, ty, nt);
 }
 Fn3 pick_moments(const cmlb3_ctx* c) {
     if (c->prec == CMLB_FP64) return pick_moments_t<double, double>(c->flow, c->walls);
@@ -219,6 +239,7 @@ StepArgs3 args3(cmlb3_ctx* c, int parity, bool moments) {
     a.tile_base = 0;
     a.ntiles = moments ? c->n_mtiles : c->n_ctiles;
     a.xcd_remap = 1;
+    a.zseg = c->czs;
     a.ushape = c->ushape;
     a.step_in = c->d_step + parity;
     a.step_out = c->d_step + (parity ^ 1);
@@ -231,8 +252,8 @@ int launch_pair(cmlb3_ctx* c, int parity) {
     hipLaunchKernelGGL(pick_moments(c), dim3(grid_of(c->n_mtiles)), dim3(WG3), 0, c->stream, am);
     HIP3(c, hipGetLastError());
     StepArgs3 ac = args3(c, parity, false);
-    hipLaunchKernelGGL(pick_collide(c, false), dim3(grid_of(c->n_ctiles)), dim3(c->cty * c->ctz * 64),
-                       0, c->stream, ac);
+    hipLaunchKernelGGL(pick_collide(c, false), dim3(grid_of(c->n_ctiles)), dim3(c->cty * 64), 0,
+                       c->stream, ac);
     HIP3(c, hipGetLastError());
     return CMLB_OK;
 }
@@ -249,7 +270,7 @@ int build_graph3(cmlb3_ctx* c, int p) {
             memset(&np, 0, sizeof(np));
             np.func = reinterpret_cast<void*>(mom ? pick_moments(c) : pick_collide(c, false));
             np.gridDim = dim3(grid_of(mom ? c->n_mtiles : c->n_ctiles));
-            np.blockDim = dim3(mom ? WG3 : c->cty * c->ctz * 64);
+            np.blockDim = dim3(mom ? WG3 : c->cty * 64);
             np.kernelParams = kargs;
             hipGraphNode_t node;
             HIP3(c, hipGraphAddKernelNode(&node, c->graph[p], prev ? &prev : nullptr, prev ? 1 : 0,
@@ -261,14 +282,15 @@ int build_graph3(cmlb3_ctx* c, int p) {
     return CMLB_OK;
 }
 
-// collision tiles 64 x ty x tz of every simulation (z-major, then y, then x)
-std::vector<int4> collide_tiles(const std::vector<cmlb3_sim_params>& ps, int ty, int tz,
+// collision columns (64 x ty nodes, zs planes from z0) of every simulation
+// (z-major, then y, then x)
+std::vector<int4> collide_tiles(const std::vector<cmlb3_sim_params>& ps, int ty, int zs,
                                 std::vector<int>* first, std::vector<int>* count) {
     std::vector<int4> ct;
     for (int s = 0; s < (int)ps.size(); ++s) {
         const cmlb3_sim_params& p = ps[s];
         if (first) first->push_back((int)ct.size());
-        for (int z0 = 0; z0 < p.nz; z0 += tz)
+        for (int z0 = 0; z0 < p.nz; z0 += zs)
             for (int y0 = 0; y0 < p.ny; y0 += ty)
                 for (int x0 = 0; x0 < p.nx; x0 += TXW) ct.push_back(make_int4(s, x0, y0, z0));
         if (count) count->push_back((int)ct.size() - first->back());
@@ -277,7 +299,7 @@ std::vector<int4> collide_tiles(const std::vector<cmlb3_sim_params>& ps, int ty,
 }
 
 int build_ctiles3(cmlb3_ctx* c) {
-    std::vector<int4> ct = collide_tiles(c->params, c->cty, c->ctz, nullptr, nullptr);
+    std::vector<int4> ct = collide_tiles(c->params, c->cty, c->czs, nullptr, nullptr);
     if (c->d_ctiles) (void)hipFree(c->d_ctiles);
     c->d_ctiles = nullptr;
     c->n_ctiles = (int)ct.size();
@@ -406,8 +428,12 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
     c->max_vol = max_vol;
     c->max_rows = max_rows;
     c->n_mtiles = (int)mt.size();
-    std::vector<int4> ct = collide_tiles(c->params, c->cty, c->ctz, nullptr, nullptr);
-    std::vector<int4> ft = collide_tiles(c->params, FTY, FTZ, &c->ftile0, &c->fntiles);
+    c->pop_bytes = (int64_t)sb * off;
+    const Shape3 dsh = default_shape3(precision);
+    c->cty = dsh.ty;
+    c->czs = dsh.zs;
+    std::vector<int4> ct = collide_tiles(c->params, c->cty, c->czs, nullptr, nullptr);
+    std::vector<int4> ft = collide_tiles(c->params, FTY, FZS, &c->ftile0, &c->fntiles);
     c->n_ctiles = (int)ct.size();
     auto bail = [&](int code) {
         release3(c);
@@ -558,8 +584,9 @@ int cmlb3_read_fields(cmlb3_ctx* c, int32_t sim, double* phi, double* cc, double
         a.tile_base = c->ftile0[sim];
         a.ntiles = c->fntiles[sim];
         a.xcd_remap = 0;
+        a.zseg = FZS;
         a.fields_out = stage;
-        hipLaunchKernelGGL(pick_collide(c, true), dim3(c->fntiles[sim]), dim3(FTY * FTZ * 64), 0,
+        hipLaunchKernelGGL(pick_collide(c, true), dim3(c->fntiles[sim]), dim3(FTY * 64), 0,
                            c->stream, a);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
             rc = fail3(c, CMLB_EDEVICE, "field kernel failed");
@@ -671,18 +698,19 @@ int cmlb3_synchronize(cmlb3_ctx* c) {
     return sync_check3(c);
 }
 
-int cmlb3_set_tile_shape(cmlb3_ctx* c, int32_t ty, int32_t tz) {
+int cmlb3_set_tile_shape(cmlb3_ctx* c, int32_t ty, int32_t zs) {
     if (!c) return CMLB_EINVAL;
-    if (ty == 0 && tz == 0) {
-        ty = 4;
-        tz = 2;
+    if (ty == 0 && zs == 0) {
+        const Shape3 d = default_shape3(c->prec);
+        ty = d.ty;
+        zs = d.zs;
     }
     bool ok = false;
-    for (int i = 0; i < N_SHAPES3; ++i) ok |= SHAPES3[i].ty == ty && SHAPES3[i].tz == tz;
-    if (!ok) return fail3(c, CMLB_EINVAL, "collision tile 64x%dx%d not supported", ty, tz);
+    for (int i = 0; i < N_SHAPES3; ++i) ok |= SHAPES3[i].ty == ty && SHAPES3[i].zs == zs;
+    if (!ok) return fail3(c, CMLB_EINVAL, "collision column 64x%d over %d planes not supported", ty, zs);
     HIP3(c, hipStreamSynchronize(c->stream));
     c->cty = ty;
-    c->ctz = tz;
+    c->czs = zs;
     return build_ctiles3(c);
 }
 
@@ -690,9 +718,17 @@ int cmlb3_launch_options(const cmlb3_ctx* c, int32_t* shapes, int32_t cap) {
     if (!c || (!shapes && cap > 0)) return CMLB_EINVAL;
     for (int i = 0; i < N_SHAPES3 && 2 * i + 1 < cap; ++i) {
         shapes[2 * i] = SHAPES3[i].ty;
-        shapes[2 * i + 1] = SHAPES3[i].tz;
+        shapes[2 * i + 1] = SHAPES3[i].zs;
     }
     return N_SHAPES3;
+}
+
+int cmlb3_set_store_policy(cmlb3_ctx* c, int32_t policy) {
+    if (!c || policy < 0 || policy > 2) return CMLB_EINVAL;
+    HIP3(c, hipStreamSynchronize(c->stream));
+    c->store_policy = policy;
+    drop_graphs3(c);
+    return CMLB_OK;
 }
 
 int cmlb3_set_use_graph(cmlb3_ctx* c, int32_t on) {

@@ -214,8 +214,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     }
     const int4 tl = a.tiles[a.tile_base + tix];
     const SimDev* sd = a.sims + tl.x;
-    const PhysConsts<T>& k = consts<T>(sd);
+    // the simulation's constants by value: read once, into scalar registers,
+    // before any store (a population store could alias the table for all the
+    // compiler knows, and a reload after a store would wait for the store)
+    const PhysConsts<T> k = consts<T>(sd);
     const int nx = sd->nx, ny = sd->ny;
+    const uint32_t node_base = sd->node_base;
+    const int64_t ushape_off = sd->ushape_off;
     const int x0 = tl.y, y0 = tl.z;
     const int plane = nx * ny;
     const int pb = plane * SB;       // bytes per direction plane
@@ -411,7 +416,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             dP = mg[j].m0 + T(0.5) * gam;
             psi = dP + (k.P_ref - rho * K<T>::cs2);
         } else if constexpr (FLOW == FLOW_PRESCRIBED) {
-            const T* us = static_cast<const T*>(a.ushape) + sd->ushape_off;
+            const T* us = static_cast<const T*>(a.ushape) + ushape_off;
             const int ni = gy < ny ? gy * nx + lx : lx;
             ux = us[ni] * tf;
             uy = us[plane + ni] * tf;
@@ -465,7 +470,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 const int own = gy * nx + gx;
                 const int vo = own * SB;
                 uint32_t rs = 0;
-                if constexpr (Store<S>::scaled) rs = fmix32(sd->node_base + (uint32_t)own) ^ step_key;
+                if constexpr (Store<S>::scaled) rs = fmix32(node_base + (uint32_t)own) ^ step_key;
                 // moving wall: the slots of directions pointing into the wall
                 // are pulled back by this node next step (half-way
                 // bounce-back); g carries the momentum correction

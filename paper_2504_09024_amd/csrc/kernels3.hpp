@@ -10,11 +10,12 @@
 //               and keep only what the collision needs: zeroth and first
 //               moments of f and h, moments up to second order of g
 //               (18 values per node, in the compute type);
-//   k_collide3  per 64 x TY x TZ tile: phi (radius 2), c and P^ (radius 1)
-//               from the moment arrays into LDS, unit normals on the
-//               radius-1 region, then per node the interface geometry,
-//               Langmuir sigma(c), F_s, F_p, u, P and the three collisions;
-//               post-collision populations stored at the node (aligned).
+//   k_collide3  per column of 64 x TY nodes marching along z: phi (radius
+//               2), c and P^ (radius 1) planes from the moment arrays into
+//               LDS rings, unit normals on the radius-1 plane, then per node
+//               the interface geometry, Langmuir sigma(c), F_s, F_p, u, P
+//               and the three collisions; post-collision populations stored
+//               at the node (aligned).
 //
 // Splitting at the moments replaces the fused 2D kernel's halo ring, which
 // in 3D would pull 27 populations for 2-5 halo nodes per own node, by
@@ -122,7 +123,8 @@ struct StepArgs3 {
     const SimDev3* sims;
     const int4* tiles;     // (sim, x0, y0, z0)
     int32_t tile_base, ntiles;
-    int32_t xcd_remap, pad_;
+    int32_t xcd_remap;
+    int32_t zseg;          // collision: z planes per column segment
     const void* ushape;    // prescribed velocity shapes, compute type
     const int64_t* step_in;
     int64_t* step_out;
@@ -214,7 +216,9 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
     if (tix >= a.ntiles) return;
     const int4 tl = a.tiles[a.tile_base + tix];
     const SimDev3* sd = a.sims + tl.x;
-    const Consts3<T>& k = consts3<T>(sd);
+    // constants by value: read once, before any store (a store could alias
+    // the table for all the compiler knows)
+    const Consts3<T> k = consts3<T>(sd);
     const int nx = sd->nx, ny = sd->ny, nz = sd->nz;
     // a moments tile is 64 columns of MT_ROWS consecutive (y, z) rows,
     // rows numbered z ny + y; tl.z is its first row
@@ -231,42 +235,46 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
     const char* srcb = static_cast<const char*>(a.src) + sd->off * SB;
     const bool inner = x >= 1 && x + 1 < nx && y >= 1 && y + 1 < ny && z >= 1 && z + 1 < nz;
     T* mom = static_cast<T*>(a.mom) + sd->moff + ((z * ny + y) * nx + x);
+    // all pulls before the first store: a load issued after a store would
+    // wait for that store as well
     T v[27];
-    T m0, jx, jy, jz;
+    T fm[4], hm[4];
     pull27<S, T, WALLS>(make_rsrc(srcb, lb), pb, x, y, z, nx, ny, nz, inner, v);
-    scalar_moments27(v, m0, jx, jy, jz);
-    mom[0] = m0;
-    mom[vol] = jx * k.inv_f;
-    mom[2 * vol] = jy * k.inv_f;
-    mom[3 * vol] = jz * k.inv_f;
+    scalar_moments27(v, fm[0], fm[1], fm[2], fm[3]);
     pull27<S, T, WALLS>(make_rsrc(srcb + lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
-    scalar_moments27(v, m0, jx, jy, jz);
-    mom[4 * vol] = m0;
-    mom[5 * vol] = jx * k.inv_h;
-    mom[6 * vol] = jy * k.inv_h;
-    mom[7 * vol] = jz * k.inv_h;
+    scalar_moments27(v, hm[0], hm[1], hm[2], hm[3]);
+    T r0 = T(0), r1[3] = {T(0), T(0), T(0)}, r2[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if constexpr (CPL) {
         pull27<S, T, WALLS>(make_rsrc(srcb + 2 * lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
         // deviations d_a = w_a s_a / scale and their raw moments
-        T r0 = T(0), r1[3] = {T(0), T(0), T(0)}, r2[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         {
 #pragma clang fp contract(off)
 #pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                const T d = Store<S>::scaled ? wgt3<T>(q) * (v[q] * k.inv_g) : wgt3<T>(q) * v[q];
-                const int ex = EXd(q), ey = EYd(q), ez = EZd(q);
-                r0 += d;
-                if (ex) r1[0] += ex > 0 ? d : -d;
-                if (ey) r1[1] += ey > 0 ? d : -d;
-                if (ez) r1[2] += ez > 0 ? d : -d;
-                if (ex) r2[0] += d;
-                if (ey) r2[1] += d;
-                if (ez) r2[2] += d;
-                if (ex && ey) r2[3] += ex * ey > 0 ? d : -d;
-                if (ex && ez) r2[4] += ex * ez > 0 ? d : -d;
-                if (ey && ez) r2[5] += ey * ez > 0 ? d : -d;
-            }
+        for (int q = 0; q < 27; ++q) {
+            const T d = Store<S>::scaled ? wgt3<T>(q) * (v[q] * k.inv_g) : wgt3<T>(q) * v[q];
+            const int ex = EXd(q), ey = EYd(q), ez = EZd(q);
+            r0 += d;
+            if (ex) r1[0] += ex > 0 ? d : -d;
+            if (ey) r1[1] += ey > 0 ? d : -d;
+            if (ez) r1[2] += ez > 0 ? d : -d;
+            if (ex) r2[0] += d;
+            if (ey) r2[1] += d;
+            if (ez) r2[2] += d;
+            if (ex && ey) r2[3] += ex * ey > 0 ? d : -d;
+            if (ex && ez) r2[4] += ex * ez > 0 ? d : -d;
+            if (ey && ez) r2[5] += ey * ez > 0 ? d : -d;
         }
+        }
+    }
+    mom[0] = fm[0];
+    mom[vol] = fm[1] * k.inv_f;
+    mom[2 * vol] = fm[2] * k.inv_f;
+    mom[3 * vol] = fm[3] * k.inv_f;
+    mom[4 * vol] = hm[0];
+    mom[5 * vol] = hm[1] * k.inv_h;
+    mom[6 * vol] = hm[2] * k.inv_h;
+    mom[7 * vol] = hm[3] * k.inv_h;
+    if constexpr (CPL) {
         mom[8 * vol] = r0;
 #pragma unroll
         for (int i = 0; i < 3; ++i) mom[(9 + i) * vol] = r1[i];
@@ -402,18 +410,21 @@ __device__ __forceinline__ void flow_dev27(const T eta2[6], T dP, T rho, T ux, T
     inverse27(t, ux, uy, uz);
 }
 
-// Isotropic D3Q27 gradient from an LDS box of row pitch PX and plane pitch
-// PXY: d_i = (1/cs2) sum_a w_a e_ai F(x + e_a).
-// No FP contraction in the stencils: a value computed at a node must carry
-// the same bits whichever tile shape (kernel instance) computes it.
-template <class T, int PX, int PXY>
-__device__ __forceinline__ void lds_grad3(const T* L, int idx, T& gx, T& gy, T& gz) {
+// Isotropic D3Q27 stencils at in-plane index idx of three LDS planes
+// (z - 1, z, z + 1; row pitch PX): gradient d_i = (1/cs2) sum_a w_a e_ai
+// F(x + e_a) and divergence (1/cs2) sum_a w_a e_a . V(x + e_a).
+// No FP contraction: a value computed at a node carries the same bits
+// whichever kernel instance (launch shape) computes it.
+template <class T, int PX>
+__device__ __forceinline__ void grad3p(const T* Lm, const T* L0, const T* Lp, int idx, T& gx,
+                                       T& gy, T& gz) {
 #pragma clang fp contract(off)
     T sx = T(0), sy = T(0), sz = T(0);
 #pragma unroll
     for (int a = 1; a < 27; ++a) {
         const int ex = EXd(a), ey = EYd(a), ez = EZd(a);
-        const T v = wgt3<T>(a) * L[idx + ex + ey * PX + ez * PXY];
+        const T* L = ez < 0 ? Lm : (ez > 0 ? Lp : L0);
+        const T v = wgt3<T>(a) * L[idx + ex + ey * PX];
         if (ex) sx += ex > 0 ? v : -v;
         if (ey) sy += ey > 0 ? v : -v;
         if (ez) sz += ez > 0 ? v : -v;
@@ -423,28 +434,16 @@ __device__ __forceinline__ void lds_grad3(const T* L, int idx, T& gx, T& gy, T& 
     gz = T(3) * sz;
 }
 
-// n = grad phi/(|grad phi| + eps), contraction off like the stencils
-template <class T, int PX, int PXY>
-__device__ __forceinline__ void unit_normal3(const T* L, int idx, T n[3]) {
-#pragma clang fp contract(off)
-    T gx, gy, gz;
-    lds_grad3<T, PX, PXY>(L, idx, gx, gy, gz);
-    const T inv = rcp_(sqrt_(gx * gx + gy * gy + gz * gz) + T(NORMAL_EPS3));
-    n[0] = gx * inv;
-    n[1] = gy * inv;
-    n[2] = gz * inv;
-}
-
-// Divergence of a vector field stored as three LDS planes (pitch NP apart)
-// with the same stencil: (1/cs2) sum_a w_a e_a . V(x + e_a).
-template <class T, int PX, int PXY, int NP>
-__device__ __forceinline__ T lds_div3(const T* V, int idx) {
+// components of V are NP apart in each plane
+template <class T, int PX, int NP>
+__device__ __forceinline__ T div3p(const T* Vm, const T* V0, const T* Vp, int idx) {
 #pragma clang fp contract(off)
     T s = T(0);
 #pragma unroll
     for (int a = 1; a < 27; ++a) {
         const int ex = EXd(a), ey = EYd(a), ez = EZd(a);
-        const int j = idx + ex + ey * PX + ez * PXY;
+        const T* V = ez < 0 ? Vm : (ez > 0 ? Vp : V0);
+        const int j = idx + ex + ey * PX;
         T d = T(0);
         if (ex) d += ex > 0 ? V[j] : -V[j];
         if (ey) d += ey > 0 ? V[NP + j] : -V[NP + j];
@@ -454,235 +453,403 @@ __device__ __forceinline__ T lds_div3(const T* V, int idx) {
     return T(3) * s;
 }
 
+// n = grad phi/(|grad phi| + eps)
+template <class T>
+__device__ __forceinline__ void unit3(T gx, T gy, T gz, T n[3]) {
+#pragma clang fp contract(off)
+    const T inv = rcp_(sqrt_(gx * gx + gy * gy + gz * gz) + T(NORMAL_EPS3));
+    n[0] = gx * inv;
+    n[1] = gy * inv;
+    n[2] = gz * inv;
+}
+
 // ---------------------------------------------------------------------------
-// k_collide3: tile 64 x TY x TZ, one node per thread (NW = TY*TZ waves).
+// k_collide3: a column of 64 x TY nodes marching through a.zseg consecutive
+// z planes, one node per thread and plane (TY waves).  Rings in LDS along z:
+//   phi     4 planes of (64 + 4) x (TY + 4)   (radius 2: normals at z +- 1)
+//   c, P^   4 planes of (64 + 2) x (TY + 2)   (radius 1)
+//   n       3 planes x 3 components of (64 + 2) x (TY + 2)
+//   grad phi of the column's own nodes, 2 planes
+// Step z:  [barrier] unit normals of plane z + 1 (phi planes z .. z + 2);
+//          loads of phi plane z + 3 and c, P^ plane z + 2 issued into
+//          registers;  [barrier]  the node collisions of plane z, with the
+//          loaded planes written into the ring slots whose planes were last
+//          read before this step's first barrier.
+// Memory-counter waits are in issue order (a wait for a load also waits for
+// every store issued before it), so the node reads all its moments and
+// hands the prefetched planes to LDS before its first population store.
+// Every plane of the three fields is read from the moment arrays once per
+// column, and unit normals are computed once per node of the radius-1 plane.
 // ---------------------------------------------------------------------------
 template <class T, int NW>
 struct Occ3 {
-    static constexpr int waves_per_eu = sizeof(T) == 4 ? 2 : 1;
+    // waves per SIMD the register budget is sized for
+    static constexpr int waves_per_eu = sizeof(T) == 4 ? (NW <= 4 ? 3 : 2) : (NW <= 4 ? 1 : 2);
 };
 
-template <class S, class T, int FLOW, bool WALLS, int TY, int TZ, bool FIELDS, bool NTS>
-__global__ __launch_bounds__(TY* TZ * 64, (Occ3<T, TY * TZ>::waves_per_eu)) void k_collide3(
+template <class S, class T, int FLOW, bool WALLS, int TY, bool FIELDS, bool NTS>
+__global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collide3(
     const StepArgs3 a) {
-    constexpr int NT = TY * TZ * 64;
+    constexpr int NT = TY * 64;
     constexpr int CP = NTS ? CPOL_NT : 0;
     constexpr bool CPL = FLOW == FLOW_COUPLED;
     constexpr bool MOV = FLOW != FLOW_NONE;
-    constexpr int PX = TXW + 4, PY = TY + 4, PZ = TZ + 4;  // phi box (radius 2)
-    constexpr int QX = TXW + 2, QY = TY + 2, QZ = TZ + 2;  // c, P^, n box (radius 1)
+    constexpr int PX = TXW + 4, PY = TY + 4, PP = PX * PY;  // phi plane (radius 2)
+    constexpr int QX = TXW + 2, QY = TY + 2, QP = QX * QY;  // c, P^, n plane (radius 1)
+    constexpr int NPH = (PP + NT - 1) / NT;                 // phi loads per thread and plane
+    constexpr int NQ = (QP + NT - 1) / NT;                  // c (P^) loads per thread and plane
     constexpr int SB = sizeof(S);
-    __shared__ T phiL[PX * PY * PZ];
-    __shared__ T cL[QX * QY * QZ];
-    __shared__ T pL[CPL ? QX * QY * QZ : 1];
-    __shared__ T nL[CPL ? 3 * QX * QY * QZ : 1];
+    __shared__ T phiL[4 * PP];
+    __shared__ T cL[4 * QP];
+    __shared__ T pL[CPL ? 4 * QP : 1];
+    __shared__ T nL[CPL ? 9 * QP : 1];
+    __shared__ T gL[2 * 3 * NT];
 
     const int tix = tile_index(a);
     if (tix >= a.ntiles) return;
     const int4 tl = a.tiles[a.tile_base + tix];
     const SimDev3* sd = a.sims + tl.x;
-    const Consts3<T>& k = consts3<T>(sd);
+    // the simulation's constants by value: read once, before any store (a
+    // population store could alias the table for all the compiler knows, and
+    // a reload after each store would wait for that store to complete)
+    const Consts3<T> k = consts3<T>(sd);
     const int nx = sd->nx, ny = sd->ny, nz = sd->nz;
+    const bool uni_rho = sd->uniform_rho, uni_nu = sd->uniform_nu;
+    const int64_t soff = sd->off;
+    const uint32_t node_base = sd->node_base;
+    const double vel_T = sd->vel_period_T;
+    const int64_t uoff = sd->uoff;
     const int x0 = tl.y, y0 = tl.z, z0 = tl.w;
+    const int zend = min(z0 + a.zseg, nz);
     const int plane = nx * ny, vol = plane * nz;
     const T* mom = static_cast<const T*>(a.mom) + sd->moff;
     const int64_t step = *a.step_in;
     const int tid = threadIdx.x;
 
-    // ---------------- LDS boxes from the moment arrays ---------------------
-    for (int i = tid; i < PX * PY * PZ; i += NT) {
-        const int rz = i / (PX * PY), rem = i - rz * PX * PY, ry = rem / PX, rx = rem - ry * PX;
+    // in-plane offsets of this thread's share of the phi and c, P^ planes
+    // (x periodic; y periodic or mirrored at the walls); -1 past the plane
+    int po[NPH], qo[NQ];
+#pragma unroll
+    for (int j = 0; j < NPH; ++j) {
+        const int i = tid + j * NT;
+        const int ry = i / PX, rx = i - ry * PX;
         const int gx = wrap_coord(x0 - 2 + rx, nx);
         const int gy = WALLS ? mirror_coord(y0 - 2 + ry, ny) : wrap_coord(y0 - 2 + ry, ny);
-        const int gz = wrap_coord(z0 - 2 + rz, nz);
-        const int n = (gz * ny + gy) * nx + gx;
-        phiL[i] = mom[n] * k.inv_f + k.qref_f;
-        const bool r1 = rx >= 1 && rx <= PX - 2 && ry >= 1 && ry <= PY - 2 && rz >= 1 && rz <= PZ - 2;
-        if (r1) {
-            const int q = ((rz - 1) * QY + (ry - 1)) * QX + (rx - 1);
-            cL[q] = mom[4 * vol + n] * k.inv_h;
-            if constexpr (CPL) pL[q] = mom[8 * vol + n];
-        }
+        po[j] = i < PP ? gy * nx + gx : -1;
     }
-    __syncthreads();
-    if constexpr (CPL) {
-        for (int i = tid; i < QX * QY * QZ; i += NT) {
-            const int qz = i / (QX * QY), rem = i - qz * QX * QY, qy = rem / QX, qx = rem - qy * QX;
-            T n3[3];
-            unit_normal3<T, PX, PX * PY>(phiL, ((qz + 1) * PY + qy + 1) * PX + qx + 1, n3);
-            nL[i] = n3[0];
-            nL[QX * QY * QZ + i] = n3[1];
-            nL[2 * QX * QY * QZ + i] = n3[2];
-        }
-        __syncthreads();
-    }
-
-    // ---------------- per node ---------------------------------------------
-    const int lx = tid & 63, r = tid >> 6;
-    const int ly = r % TY, lz = r / TY;
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    const bool valid = gx < nx && gy < ny && gz < nz;
-    if (!valid) return;
-    const int own = (gz * ny + gy) * nx + gx;
-    const int pidx = ((lz + 2) * PY + ly + 2) * PX + lx + 2;
-    const int qidx = ((lz + 1) * QY + ly + 1) * QX + lx + 1;
-    const T phi = phiL[pidx], c = cL[qidx];
-    T gpx, gpy, gpz;
-    lds_grad3<T, PX, PX * PY>(phiL, pidx, gpx, gpy, gpz);
-    const T gm2 = gpx * gpx + gpy * gpy + gpz * gpz;
-    T nxv, nyv, nzv;
-    if constexpr (CPL) {
-        nxv = nL[qidx];
-        nyv = nL[QX * QY * QZ + qidx];
-        nzv = nL[2 * QX * QY * QZ + qidx];
-    } else {
-        T n3[3];
-        unit_normal3<T, PX, PX * PY>(phiL, pidx, n3);
-        nxv = n3[0];
-        nyv = n3[1];
-        nzv = n3[2];
-    }
-    const T theta = k.theta_k * (k.phi_a - phi) * (phi - k.phi_b) * k.inv_dphi;
-    const T theta_c = k.thetac_k * c * (k.phim - phi) * k.inv_dphi;
-    T ux = T(0), uy = T(0), uz = T(0), dP = T(0), rho = T(1), om_nu = T(1);
-    T fp[3] = {T(0), T(0), T(0)}, ft[3] = {T(0), T(0), T(0)}, gam = T(0);
-    int fault = 0;
-    if constexpr (CPL) {
-        T gc[3], gq[3];
-        // curvature: divergence of the unit normal, same stencil
-        const T curv = lds_div3<T, QX, QX * QY, QX * QY * QZ>(nL, qidx);
-        lds_grad3<T, QX, QX * QY>(cL, qidx, gc[0], gc[1], gc[2]);
-        lds_grad3<T, QX, QX * QY>(pL, qidx, gq[0], gq[1], gq[2]);
-        const T lam = (phi - k.phi_b) * k.inv_dphi;
-        rho = sd->uniform_rho ? k.rho_b : k.rho_b + lam * k.drho;
-        const T inv_rho = sd->uniform_rho ? k.inv_rho_b : rcp_(rho);
-        om_nu = sd->uniform_nu ? k.omega_nu_b : rcp_(T(3) * (k.nu_b + lam * k.dnu) + T(0.5));
-        const T arg = T(1) - c * k.inv_cmax;
-        const T sigma = k.sigma0 * (T(1) + k.beta * log_(arg));
-        if (!(arg > T(0)) || !(sigma >= T(0))) fault |= 2;
-        const T dsig = -k.sigma0 * k.beta * rcp_(k.c_max - c);
-        const T gs[3] = {dsig * gc[0], dsig * gc[1], dsig * gc[2]};
-        const T n3[3] = {nxv, nyv, nzv};
-        const T nd = nxv * gs[0] + nyv * gs[1] + nzv * gs[2];
-        const T wk = k.ks * gm2;
-        const T fe[3] = {k.Fx, k.Fy, k.Fz};
-        const T gp[3] = {gpx, gpy, gpz};
-        const T j[3] = {mom[9 * vol + own], mom[10 * vol + own], mom[11 * vol + own]};
-        T u[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ft[i] = wk * ((gs[i] - n3[i] * nd) - sigma * curv * n3[i]) + fe[i];
-            // F_p = -grad psi^, psi^ = P^ - rho cs2, rho linear in phi
-            fp[i] = -(gq[i] - k.dr_cs2 * gp[i]);
-            u[i] = (T(3) * j[i] + T(0.5) * ft[i]) * inv_rho;
-        }
-        ux = u[0];
-        uy = u[1];
-        uz = u[2];
-        gam = fp[0] * ux + fp[1] * uy + fp[2] * uz;
-        dP = mom[8 * vol + own] + T(0.5) * gam;
-    } else if constexpr (FLOW == FLOW_PRESCRIBED) {
-        const T tf = sd->vel_period_T != 0.0 ? T(cos(M_PI * (double)step / sd->vel_period_T)) : T(1);
-        const T* us = static_cast<const T*>(a.ushape) + sd->uoff;
-        ux = us[own] * tf;
-        uy = us[vol + own] * tf;
-        uz = us[2 * vol + own] * tf;
+    for (int j = 0; j < NQ; ++j) {
+        const int i = tid + j * NT;
+        const int ry = i / QX, rx = i - ry * QX;
+        const int gx = wrap_coord(x0 - 1 + rx, nx);
+        const int gy = WALLS ? mirror_coord(y0 - 1 + ry, ny) : wrap_coord(y0 - 1 + ry, ny);
+        qo[j] = i < QP ? gy * nx + gx : -1;
     }
-    if (!isfinite(phi + c + ux + uy + uz + dP)) fault |= 1;
-    if (fault) atomicOr(a.fault + tl.x, fault);
-
-    if constexpr (FIELDS) {
-        double* o = a.fields_out;
-        o[own] = double(phi);
-        o[vol + own] = double(c);
-        o[2 * vol + own] = double(ux);
-        o[3 * vol + own] = double(uy);
-        o[4 * vol + own] = double(uz);
-        o[5 * vol + own] = CPL ? double(k.P_ref) + double(dP) : 0.0;
-        return;
-    } else {
-        if (blockIdx.x == 0 && tid == 0) *a.step_out = step + 1;
-        const int lb = 27 * vol * SB;
-        char* dstb = static_cast<char*>(a.dst) + sd->off * SB;
-        const int vo = own * SB;
-        const int pb = vol * SB;
-        uint32_t rs = 0;
-        if constexpr (Store<S>::scaled) {
-            const uint32_t key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
-            rs = fmix32(sd->node_base + (uint32_t)own) ^ key;
-        }
-        T t[27];
-        // f: phase field
-        {
-            const T m0 = mom[own];
-            const T jx = mom[vol + own], jy = mom[2 * vol + own], jz = mom[3 * vol + own];
-            const T om = k.omega_k, mt = k.M_phi * theta;
-            const T k1x = (T(1) - om) * (jx - ux * phi) + om * mt * nxv;
-            const T k1y = (T(1) - om) * (jy - uy * phi) + om * mt * nyv;
-            const T k1z = (T(1) - om) * (jz - uz * phi) + om * mt * nzv;
-            scalar_dev27<T, MOV>(phi, k1x, k1y, k1z, ux, uy, uz, t);
-            const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb, lb);
+    // ring slots
+    auto ps = [&](int zz) { return ((zz - z0 + 2) & 3) * PP; };
+    auto cs = [&](int zz) { return ((zz - z0 + 1) & 3) * QP; };
+    auto ns = [&](int zz) { return ((zz - z0 + 1) % 3) * 3 * QP; };
+    auto gs = [&](int zz) { return ((zz - z0) & 1) * 3 * NT; };
+    auto zbase = [&](int zz) { return wrap_coord(zz, nz) * plane; };
+    // plane loads are issued unconditionally at clamped addresses (in
+    // bounds) and all land in registers before the first LDS write, so a
+    // prologue of several planes waits for memory once
+    auto load_phi = [&](int zz, T v[NPH]) {
+        const int b = zbase(zz);
 #pragma unroll
-            for (int q = 0; q < 27; ++q)
-                Buf<S>::template store<CP>(w, vo, q * pb, m0 + k.scale_f * t[q] * inv_wgt3<T>(q),
-                                           rs + weyl(3 * q));
-        }
-        // h: surfactant
-        {
-            const T m0 = mom[4 * vol + own];
-            const T jx = mom[5 * vol + own], jy = mom[6 * vol + own], jz = mom[7 * vol + own];
-            const T om = k.omega_c, mt = k.D_s * theta_c;
-            const T k1x = (T(1) - om) * (jx - ux * c) + om * mt * nxv;
-            const T k1y = (T(1) - om) * (jy - uy * c) + om * mt * nyv;
-            const T k1z = (T(1) - om) * (jz - uz * c) + om * mt * nzv;
-            scalar_dev27<T, MOV>(c, k1x, k1y, k1z, ux, uy, uz, t);
-            const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + lb, lb);
+        for (int j = 0; j < NPH; ++j) v[j] = mom[b + max(po[j], 0)];
+    };
+    auto store_phi = [&](int zz, const T v[NPH]) {
+        const int s = ps(zz);
 #pragma unroll
-            for (int q = 0; q < 27; ++q)
-                Buf<S>::template store<CP>(w, vo, q * pb, m0 + k.scale_h * t[q] * inv_wgt3<T>(q),
-                                           rs + weyl(3 * q + 1));
+        for (int j = 0; j < NPH; ++j)
+            if (po[j] >= 0) phiL[s + tid + j * NT] = v[j] * k.inv_f + k.qref_f;
+    };
+    auto load_cp = [&](int zz, T vc[NQ], T vp[NQ]) {
+        const int b = zbase(zz);
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            vc[j] = mom[4 * vol + b + max(qo[j], 0)];
+            if constexpr (CPL) vp[j] = mom[8 * vol + b + max(qo[j], 0)];
         }
-        // g: flow
+    };
+    auto store_cp = [&](int zz, const T vc[NQ], const T vp[NQ]) {
+        const int s = cs(zz);
+#pragma unroll
+        for (int j = 0; j < NQ; ++j)
+            if (qo[j] >= 0) {
+                cL[s + tid + j * NT] = vc[j] * k.inv_h;
+                if constexpr (CPL) pL[s + tid + j * NT] = vp[j];
+            }
+    };
+    // unit normals of plane zz on the radius-1 plane (coupled) and grad phi
+    // at the own nodes; needs phi planes zz - 1 .. zz + 1
+    auto normals = [&](int zz) {
+        const T* Lm = phiL + ps(zz - 1);
+        const T* L0 = phiL + ps(zz);
+        const T* Lp = phiL + ps(zz + 1);
         if constexpr (CPL) {
-            const T r0 = mom[8 * vol + own];
-            const T j[3] = {mom[9 * vol + own], mom[10 * vol + own], mom[11 * vol + own]};
-            T r2[6];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) r2[i] = mom[(12 + i) * vol + own];
-            // central second moments of the deviations about u
-            const T u[3] = {ux, uy, uz};
-            T eta2[6];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) eta2[i] = r2[i] - T(2) * u[i] * j[i] + u[i] * u[i] * r0;
-            eta2[3] = r2[3] - u[0] * j[1] - u[1] * j[0] + u[0] * u[1] * r0;
-            eta2[4] = r2[4] - u[0] * j[2] - u[2] * j[0] + u[0] * u[2] * r0;
-            eta2[5] = r2[5] - u[1] * j[2] - u[2] * j[1] + u[1] * u[2] * r0;
-            flow_dev27<T>(eta2, dP, rho, ux, uy, uz, fp, ft, gam, k.omega_zeta, om_nu, t);
-            // moving wall: slots of directions pointing into the wall are
-            // pulled back by this node next step; add 2 rho (e_opp . u_w)
-            T wcorr = T(0);
-            int wdir = 0;
-            if (WALLS) {
-                if (gy == 0) {
-                    wdir = -1;
-                    wcorr = T(2) * rho * k.u_wall * k.scale_g;
-                }
-                if (gy == ny - 1) {
-                    wdir = 1;
-                    wcorr = -T(2) * rho * k.u_wall * k.scale_g;
+            T* N = nL + ns(zz);
+            for (int i = tid; i < QP; i += NT) {
+                const int qy = i / QX, qx = i - qy * QX;
+                T g[3], n3[3];
+                grad3p<T, PX>(Lm, L0, Lp, (qy + 1) * PX + qx + 1, g[0], g[1], g[2]);
+                unit3(g[0], g[1], g[2], n3);
+                N[i] = n3[0];
+                N[QP + i] = n3[1];
+                N[2 * QP + i] = n3[2];
+                if (qx >= 1 && qx <= TXW && qy >= 1 && qy <= TY) {
+                    const int o = (qy - 1) * TXW + qx - 1;
+                    T* G = gL + gs(zz);
+                    G[o] = g[0];
+                    G[NT + o] = g[1];
+                    G[2 * NT + o] = g[2];
                 }
             }
-            const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + 2 * lb, lb);
+        } else {
+            const int ly = tid >> 6, lx = tid & 63;
+            T g[3];
+            grad3p<T, PX>(Lm, L0, Lp, (ly + 2) * PX + lx + 2, g[0], g[1], g[2]);
+            T* G = gL + gs(zz);
+            G[tid] = g[0];
+            G[NT + tid] = g[1];
+            G[2 * NT + tid] = g[2];
+        }
+    };
+
+    // ---------------- prologue ---------------------------------------------
+    {
+        T v[4][NPH], vc[3][NQ], vp[3][NQ];
 #pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                T v = k.scale_g * t[q] * inv_wgt3<T>(q);
-                if (WALLS && wdir != 0 && EYd(q) == wdir) v += wcorr * T(EXd(q));
-                Buf<S>::template store<CP>(w, vo, q * pb, v, rs + weyl(3 * q + 2));
+        for (int i = 0; i < 4; ++i) load_phi(z0 - 2 + i, v[i]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) load_cp(z0 - 1 + i, vc[i], vp[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) store_phi(z0 - 2 + i, v[i]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) store_cp(z0 - 1 + i, vc[i], vp[i]);
+    }
+    {
+        T v[NPH];
+        load_phi(z0 + 2, v);
+        __syncthreads();
+        if constexpr (CPL) normals(z0 - 1);  // only the normals of plane z0 - 1 are used
+        normals(z0);
+        __syncthreads();
+        store_phi(z0 + 2, v);  // into the slot of plane z0 - 2
+    }
+
+    const int lx = tid & 63, ly = tid >> 6;
+    const int gx = x0 + lx, gy = y0 + ly;
+    const bool col_ok = gx < nx && gy < ny;
+    const int pidx = (ly + 2) * PX + lx + 2;
+    const int qidx = (ly + 1) * QX + lx + 1;
+    if (!FIELDS && blockIdx.x == 0 && tid == 0) *a.step_out = step + 1;
+    int fault = 0;
+
+    for (int z = z0; z < zend; ++z) {
+        __syncthreads();
+        normals(z + 1);
+        // phi plane z + 3 and c, P^ plane z + 2 into registers (issued on
+        // every step, in bounds: at a segment's last step they go unused)
+        T fphi[NPH], fc[NQ], fp_[NQ];
+        load_phi(z + 3, fphi);
+        load_cp(z + 2, fc, fp_);
+        __syncthreads();
+        // ... and into the ring slots of planes z - 1 (phi) and z - 2 (c, P^),
+        // whose last readers passed this step's first barrier.  Called after
+        // the node's LDS reads and before its population stores: waiting for
+        // these loads then waits for no store of this plane.
+        auto flush = [&]() {
+            store_phi(z + 3, fphi);
+            store_cp(z + 2, fc, fp_);
+        };
+
+        {
+            // ---------------- per node ---------------------------------------
+            // idle lanes of a ragged column work on clamped, in-bounds data
+            // and store nothing
+            const int own = z * plane + min(gy, ny - 1) * nx + min(gx, nx - 1);
+            const T phi = phiL[ps(z) + pidx], c = cL[cs(z) + qidx];
+            const T* G = gL + gs(z);
+            const T gpx = G[tid], gpy = G[NT + tid], gpz = G[2 * NT + tid];
+            const T gm2 = gpx * gpx + gpy * gpy + gpz * gpz;
+            T nxv, nyv, nzv;
+            if constexpr (CPL) {
+                const T* N = nL + ns(z);
+                nxv = N[qidx];
+                nyv = N[QP + qidx];
+                nzv = N[2 * QP + qidx];
+            } else {
+                T n3[3];
+                unit3(gpx, gpy, gpz, n3);
+                nxv = n3[0];
+                nyv = n3[1];
+                nzv = n3[2];
+            }
+            const T theta = k.theta_k * (k.phi_a - phi) * (phi - k.phi_b) * k.inv_dphi;
+            const T theta_c = k.thetac_k * c * (k.phim - phi) * k.inv_dphi;
+            T ux = T(0), uy = T(0), uz = T(0), dP = T(0), rho = T(1), om_nu = T(1);
+            T fp[3] = {T(0), T(0), T(0)}, ft[3] = {T(0), T(0), T(0)}, gam = T(0);
+            T r0g = T(0), jg[3] = {T(0), T(0), T(0)};  // g moments of the node
+            int nfault = 0;
+            if constexpr (CPL) {
+                T gc[3], gq[3];
+                // curvature: divergence of the unit normal, same stencil
+                const T curv = div3p<T, QX, QP>(nL + ns(z - 1), nL + ns(z), nL + ns(z + 1), qidx);
+                grad3p<T, QX>(cL + cs(z - 1), cL + cs(z), cL + cs(z + 1), qidx, gc[0], gc[1],
+                              gc[2]);
+                grad3p<T, QX>(pL + cs(z - 1), pL + cs(z), pL + cs(z + 1), qidx, gq[0], gq[1],
+                              gq[2]);
+                const T lam = (phi - k.phi_b) * k.inv_dphi;
+                rho = uni_rho ? k.rho_b : k.rho_b + lam * k.drho;
+                const T inv_rho = uni_rho ? k.inv_rho_b : rcp_(rho);
+                om_nu = uni_nu ? k.omega_nu_b : rcp_(T(3) * (k.nu_b + lam * k.dnu) + T(0.5));
+                const T arg = T(1) - c * k.inv_cmax;
+                const T sigma = k.sigma0 * (T(1) + k.beta * log_(arg));
+                if (!(arg > T(0)) || !(sigma >= T(0))) nfault |= 2;
+                const T dsig = -k.sigma0 * k.beta * rcp_(k.c_max - c);
+                const T gsg[3] = {dsig * gc[0], dsig * gc[1], dsig * gc[2]};
+                const T n3[3] = {nxv, nyv, nzv};
+                const T nd = nxv * gsg[0] + nyv * gsg[1] + nzv * gsg[2];
+                const T wk = k.ks * gm2;
+                const T fe[3] = {k.Fx, k.Fy, k.Fz};
+                const T gp[3] = {gpx, gpy, gpz};
+                r0g = mom[8 * vol + own];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) jg[i] = mom[(9 + i) * vol + own];
+                T u[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    ft[i] = wk * ((gsg[i] - n3[i] * nd) - sigma * curv * n3[i]) + fe[i];
+                    // F_p = -grad psi^, psi^ = P^ - rho cs2, rho linear in phi
+                    fp[i] = -(gq[i] - k.dr_cs2 * gp[i]);
+                    u[i] = (T(3) * jg[i] + T(0.5) * ft[i]) * inv_rho;
+                }
+                ux = u[0];
+                uy = u[1];
+                uz = u[2];
+                gam = fp[0] * ux + fp[1] * uy + fp[2] * uz;
+                dP = r0g + T(0.5) * gam;
+            } else if constexpr (FLOW == FLOW_PRESCRIBED) {
+                const T tf = vel_T != 0.0 ? T(cos(M_PI * (double)step / vel_T)) : T(1);
+                const T* us = static_cast<const T*>(a.ushape) + uoff;
+                ux = us[own] * tf;
+                uy = us[vol + own] * tf;
+                uz = us[2 * vol + own] * tf;
+            }
+            if (!isfinite(phi + c + ux + uy + uz + dP)) nfault |= 1;
+            // every moment of the node is read, and the prefetched planes are
+            // in LDS, before the first population store; the empty asm keeps
+            // the compiler from sinking either below the stores
+            T mf[4], mh[4], r2[6];
+            if constexpr (!FIELDS) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    mf[i] = mom[i * vol + own];
+                    mh[i] = mom[(4 + i) * vol + own];
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) r2[i] = CPL ? mom[(12 + i) * vol + own] : T(0);
+            }
+            flush();
+            asm volatile("" ::: "memory");
+
+            if (!col_ok) {
+                // nothing to store
+            } else if constexpr (FIELDS) {
+                fault |= nfault;
+                double* o = a.fields_out;
+                o[own] = double(phi);
+                o[vol + own] = double(c);
+                o[2 * vol + own] = double(ux);
+                o[3 * vol + own] = double(uy);
+                o[4 * vol + own] = double(uz);
+                o[5 * vol + own] = CPL ? double(k.P_ref) + double(dP) : 0.0;
+            } else {
+                fault |= nfault;
+                const int lb = 27 * vol * SB;
+                char* dstb = static_cast<char*>(a.dst) + soff * SB;
+                const int vo = own * SB;
+                const int pb = vol * SB;
+                uint32_t rs = 0;
+                if constexpr (Store<S>::scaled) {
+                    const uint32_t key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
+                    rs = fmix32(node_base + (uint32_t)own) ^ key;
+                }
+                T t[27];
+                // f: phase field
+                {
+                    const T m0 = mf[0], jx = mf[1], jy = mf[2], jz = mf[3];
+                    const T om = k.omega_k, mt = k.M_phi * theta;
+                    const T k1x = (T(1) - om) * (jx - ux * phi) + om * mt * nxv;
+                    const T k1y = (T(1) - om) * (jy - uy * phi) + om * mt * nyv;
+                    const T k1z = (T(1) - om) * (jz - uz * phi) + om * mt * nzv;
+                    scalar_dev27<T, MOV>(phi, k1x, k1y, k1z, ux, uy, uz, t);
+                    const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb, lb);
+#pragma unroll
+                    for (int q = 0; q < 27; ++q)
+                        Buf<S>::template store<CP>(w, vo, q * pb,
+                                                   m0 + k.scale_f * t[q] * inv_wgt3<T>(q),
+                                                   rs + weyl(3 * q));
+                }
+                // h: surfactant
+                {
+                    const T m0 = mh[0], jx = mh[1], jy = mh[2], jz = mh[3];
+                    const T om = k.omega_c, mt = k.D_s * theta_c;
+                    const T k1x = (T(1) - om) * (jx - ux * c) + om * mt * nxv;
+                    const T k1y = (T(1) - om) * (jy - uy * c) + om * mt * nyv;
+                    const T k1z = (T(1) - om) * (jz - uz * c) + om * mt * nzv;
+                    scalar_dev27<T, MOV>(c, k1x, k1y, k1z, ux, uy, uz, t);
+                    const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + lb, lb);
+#pragma unroll
+                    for (int q = 0; q < 27; ++q)
+                        Buf<S>::template store<CP>(w, vo, q * pb,
+                                                   m0 + k.scale_h * t[q] * inv_wgt3<T>(q),
+                                                   rs + weyl(3 * q + 1));
+                }
+                // g: flow
+                if constexpr (CPL) {
+                    const T r0 = r0g;
+                    const T j[3] = {jg[0], jg[1], jg[2]};
+                    // central second moments of the deviations about u
+                    const T u[3] = {ux, uy, uz};
+                    T eta2[6];
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        eta2[i] = r2[i] - T(2) * u[i] * j[i] + u[i] * u[i] * r0;
+                    eta2[3] = r2[3] - u[0] * j[1] - u[1] * j[0] + u[0] * u[1] * r0;
+                    eta2[4] = r2[4] - u[0] * j[2] - u[2] * j[0] + u[0] * u[2] * r0;
+                    eta2[5] = r2[5] - u[1] * j[2] - u[2] * j[1] + u[1] * u[2] * r0;
+                    flow_dev27<T>(eta2, dP, rho, ux, uy, uz, fp, ft, gam, k.omega_zeta, om_nu, t);
+                    // moving wall: slots of directions pointing into the wall
+                    // are pulled back by this node next step; add
+                    // 2 rho (e_opp . u_w)
+                    T wcorr = T(0);
+                    int wdir = 0;
+                    if (WALLS) {
+                        if (gy == 0) {
+                            wdir = -1;
+                            wcorr = T(2) * rho * k.u_wall * k.scale_g;
+                        }
+                        if (gy == ny - 1) {
+                            wdir = 1;
+                            wcorr = -T(2) * rho * k.u_wall * k.scale_g;
+                        }
+                    }
+                    const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + 2 * lb, lb);
+#pragma unroll
+                    for (int q = 0; q < 27; ++q) {
+                        T v = k.scale_g * t[q] * inv_wgt3<T>(q);
+                        if (WALLS && wdir != 0 && EYd(q) == wdir) v += wcorr * T(EXd(q));
+                        Buf<S>::template store<CP>(w, vo, q * pb, v, rs + weyl(3 * q + 2));
+                    }
+                }
             }
         }
     }
+    if (fault) atomicOr(a.fault + tl.x, fault);
 }
-
 // ---------------------------------------------------------------------------
 // Initialisation: populations at the central-moment equilibria of given
 // fields (FP64), each direction written into the slot it is pulled from.
