@@ -31,8 +31,14 @@ METRIC = "coupled MLUPS and % HBM roofline, FP32/FP16-storage/batched vs FP64 GP
 HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2}
 ARITH = {"fp64": "f64", "fp32": "f32", "fp16": "f32"}
-KERNEL_SOURCES = ("paper_2504_09024_amd/csrc/kernels.hpp", "paper_2504_09024_amd/csrc/lattice.hpp",
-                  "paper_2504_09024_amd/csrc/device_common.hpp")
+# sources whose change invalidates counter-measured traffic (the build
+# flags included), per lattice dimension
+KERNEL_SOURCES = {
+    2: ("paper_2504_09024_amd/csrc/kernels.hpp", "paper_2504_09024_amd/csrc/lattice.hpp",
+        "paper_2504_09024_amd/csrc/device_common.hpp", "paper_2504_09024_amd/build.py"),
+    3: ("paper_2504_09024_amd/csrc/kernels3.hpp", "paper_2504_09024_amd/csrc/device_common.hpp",
+        "paper_2504_09024_amd/build.py"),
+}
 
 
 def log(*a):
@@ -45,9 +51,9 @@ def algorithmic_bytes_per_node(prec, lattices=3, q=9):
     return lattices * q * 2 * STORAGE_BYTES[prec]
 
 
-def kernel_hash():
+def kernel_hash(dim=2):
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[dim]:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -99,7 +105,7 @@ def make_ctx(cmlb, sims, prec, stream, tile_rows=0, graph=True, xcd_remap=True, 
     return ctx
 
 
-def traffic_entry(workload_key, prec):
+def traffic_entry(workload_key, prec, dim=2):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -111,7 +117,7 @@ def traffic_entry(workload_key, prec):
     except (OSError, ValueError):
         return None
     ent = data.get(f"{workload_key}:{prec}")
-    if not ent or ent.get("kernel_hash") != kernel_hash():
+    if not ent or ent.get("kernel_hash") != kernel_hash(dim):
         return None
     return ent.get("bytes_per_launch")
 
@@ -133,37 +139,51 @@ def _counter_kib(csv_path, counter, kernel_substr):
 
 
 def record_traffic(key, nodes, prec, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv,
-                   copy_bytes, path=None, lattices=3):
-    """Scale the step kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by
-    what the same counters read for a plain device copy of copy_bytes, and
-    store HBM bytes per launch under `key` in profiles/traffic.json, tagged
-    with the hash of the kernel sources."""
+                   copy_bytes, path=None, lattices=3, q=9, kernels=("k_step",)):
+    """Scale the step kernels' FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
+    summed over the kernels of one step: k_step in 2D, k_moments3 and
+    k_collide3 in 3D) by what the same counters read for a plain device copy
+    of copy_bytes, and store HBM bytes per step under `key` in
+    profiles/traffic.json, tagged with the hash of the kernel sources."""
     path = path or os.path.join(ROOT, "profiles", "traffic.json")
     cf, _ = _counter_kib(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = _counter_kib(copy_write_csv, "WRITE_SIZE", "copyBuffer")
     fetch_scale = copy_bytes / (cf * 1024.0)
     write_scale = copy_bytes / (cw * 1024.0)
-    kf, nf = _counter_kib(fetch_csv, "FETCH_SIZE", "k_step")
-    kw, nw = _counter_kib(write_csv, "WRITE_SIZE", "k_step")
+    kf = kw = 0.0
+    nf, nw, per_kernel = [], [], {}
+    for kn in kernels:
+        f1, n1 = _counter_kib(fetch_csv, "FETCH_SIZE", kn)
+        w1, n2 = _counter_kib(write_csv, "WRITE_SIZE", kn)
+        kf += f1
+        kw += w1
+        nf.append(n1)
+        nw.append(n2)
+        per_kernel[kn] = {"fetch_bytes": int(round(f1 * 1024.0 * fetch_scale)),
+                          "write_bytes": int(round(w1 * 1024.0 * write_scale))}
     fetch = kf * 1024.0 * fetch_scale
     write = kw * 1024.0 * write_scale
-    alg = algorithmic_bytes_per_node(prec, lattices) * nodes
+    alg = algorithmic_bytes_per_node(prec, lattices, q) * nodes
     data = {}
     if os.path.exists(path):
         with open(path) as fh:
             data = json.load(fh)
-    data["_note"] = ("HBM-side bytes per step-kernel launch from rocprofv3 --pmc FETCH_SIZE and "
-                     "WRITE_SIZE (KiB per dispatch), each scaled by the counter's reading for a "
-                     "plain device copy (bench.py --copy-calibration).")
+    data["_note"] = ("HBM-side bytes per step (one step-kernel launch in 2D; the moments and "
+                     "collision launches in 3D) from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                     "(KiB per dispatch), each scaled by the counter's reading for a plain device "
+                     "copy (bench.py --copy-calibration).")
     data["calibration"] = {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": round(cf, 2),
                            "WRITE_SIZE_KiB": round(cw, 2), "fetch_scale": fetch_scale,
                            "write_scale": write_scale}
-    data[key] = {"kernel_hash": kernel_hash(), "bytes_per_launch": int(round(fetch + write)),
+    data[key] = {"kernel_hash": kernel_hash(3 if len(kernels) > 1 else 2),
+                 "bytes_per_launch": int(round(fetch + write)),
                  "fetch_bytes": int(round(fetch)), "write_bytes": int(round(write)),
                  "algorithmic_bytes": alg,
                  "traffic_over_algorithmic": round((fetch + write) / alg, 4),
                  "fetch_over_algorithmic_reads": round(fetch / (alg / 2), 4),
-                 "dispatches": [nf, nw]}
+                 "dispatches": [sum(nf), sum(nw)]}
+    if len(kernels) > 1:
+        data[key]["per_kernel"] = per_kernel
     with open(path, "w") as fh:
         json.dump(data, fh, indent=1)
         fh.write("\n")
@@ -175,8 +195,12 @@ def cpu_baseline(sims, target_s=12.0):
     simulation of the set, as many steps as fit ~target_s (at least 2)."""
     import oracle
     p, fl = sims[0]
-    o = oracle.OracleSim(oracle.make_params(**p), fl["phi"], fl["c"], fl.get("ux"),
-                         fl.get("uy"), fl.get("P"))
+    if "nz" in p:
+        o = oracle.OracleSim3(oracle.make_params3(**p), fl["phi"], fl["c"], fl.get("ux"),
+                              fl.get("uy"), fl.get("uz"), fl.get("P"))
+    else:
+        o = oracle.OracleSim(oracle.make_params(**p), fl["phi"], fl["c"], fl.get("ux"),
+                             fl.get("uy"), fl.get("P"))
     t0 = time.perf_counter()
     o.run(2)
     dt = time.perf_counter() - t0
@@ -188,11 +212,12 @@ def cpu_baseline(sims, target_s=12.0):
         o.run(extra)
         dt += time.perf_counter() - t1
         steps += extra
-    nodes = p["nx"] * p["ny"]
+    nodes = p["nx"] * p["ny"] * p.get("nz", 1)
+    size = "x".join(str(p[k]) for k in ("nx", "ny", "nz") if k in p)
     return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} steps of simulation 0 of the workload ({p['nx']}x{p['ny']} "
-                      f"coupled, {dt:.1f} s, FP64, OpenMP over rows)"}
+            "sample": f"{steps} steps of simulation 0 of the workload ({size} "
+                      f"{p.get('flow', 'coupled')}, {dt:.1f} s, FP64, OpenMP over rows)"}
 
 
 WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2", "c5")
@@ -280,11 +305,12 @@ def main():
     if args.record_traffic:
         from paper_2504_09024_amd import workloads as W
         sims, _ = workload(W, args.workload)
-        nodes = sum(p["nx"] * p["ny"] for p, _ in sims)
-        ent = record_traffic(f"{args.workload}:{args.precision}", nodes, args.precision,
+        dim3 = "nz" in sims[0][0]
+        ent = record_traffic(f"{args.workload}:{args.precision}", nodes_of(sims), args.precision,
                              *args.record_traffic,
                              copy_bytes=(args.copy_calibration or 1024) << 20,
-                             lattices=lattices_of(sims))
+                             lattices=lattices_of(sims), q=q_of(sims),
+                             kernels=("k_moments3", "k_collide3") if dim3 else ("k_step",))
         print(json.dumps(ent))
         return
 
@@ -409,7 +435,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_entry(args.workload, prec),
+            "traffic": traffic_entry(args.workload, prec, 3 if dim3 else 2),
         },
         "cpu_baseline": cpu,
         "forms": forms,

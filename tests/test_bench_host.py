@@ -54,5 +54,26 @@ def test_record_traffic_scales_by_copy(tmp_path):
     assert ent["algorithmic_bytes"] == 216000
     assert ent["dispatches"] == [2, 2]
     data = json.loads(out.read_text())
-    assert data["batched:fp32"]["kernel_hash"] == bench.kernel_hash()
+    assert data["batched:fp32"]["kernel_hash"] == bench.kernel_hash(2)
     assert abs(data["calibration"]["fetch_scale"] - 2.0) < 1e-12
+
+
+def test_record_traffic_sums_the_3d_step_kernels(tmp_path):
+    mom = "void cmlb3::k_moments3<float, float, 2, true>(cmlb3::StepArgs3)"
+    col = "void cmlb3::k_collide3<float, float, 2, true, 8, false, true>(cmlb3::StepArgs3)"
+    copy = "__amd_rocclr_copyBuffer"
+    _csv(tmp_path / "cf.csv", [(1, copy, "FETCH_SIZE", 512.0)])
+    _csv(tmp_path / "cw.csv", [(1, copy, "WRITE_SIZE", 1024.0)])
+    _csv(tmp_path / "f.csv", [(3, mom, "FETCH_SIZE", 100.0), (4, col, "FETCH_SIZE", 30.0),
+                              (5, mom, "FETCH_SIZE", 100.0), (6, col, "FETCH_SIZE", 10.0)])
+    _csv(tmp_path / "w.csv", [(3, mom, "WRITE_SIZE", 20.0), (4, col, "WRITE_SIZE", 80.0)])
+    out = tmp_path / "traffic.json"
+    ent = bench.record_traffic("c5:fp32", 100, "fp32", tmp_path / "f.csv", tmp_path / "w.csv",
+                               tmp_path / "cf.csv", tmp_path / "cw.csv", copy_bytes=1 << 20,
+                               path=str(out), lattices=3, q=27,
+                               kernels=("k_moments3", "k_collide3"))
+    assert ent["fetch_bytes"] == (100 + 20) * 1024 * 2
+    assert ent["write_bytes"] == (20 + 80) * 1024
+    assert ent["algorithmic_bytes"] == 3 * 27 * 2 * 4 * 100
+    assert ent["per_kernel"]["k_collide3"]["write_bytes"] == 80 * 1024
+    assert json.loads(out.read_text())["c5:fp32"]["kernel_hash"] == bench.kernel_hash(3)
