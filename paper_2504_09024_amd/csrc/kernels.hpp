@@ -21,6 +21,8 @@
 // directions that would come from behind the wall out of its own opposite
 // slots; the momentum correction of g is added when those slots are stored.
 #pragma once
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace cmlb {
@@ -214,10 +216,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     }
     const int4 tl = a.tiles[a.tile_base + tix];
     const SimDev* sd = a.sims + tl.x;
-    // the simulation's constants by value: read once, into scalar registers,
-    // before any store (a population store could alias the table for all the
-    // compiler knows, and a reload after a store would wait for the store)
-    const PhysConsts<T> k = consts<T>(sd);
+    // FP32: the simulation's constants by value, read once into scalar
+    // registers before any store (a population store could alias the table
+    // for all the compiler knows, and a reload after a store would wait for
+    // the store).  FP64 keeps reading them on use: twice the scalar
+    // registers would spill.
+    using KRef = std::conditional_t<(sizeof(T) > 4), const PhysConsts<T>&, const PhysConsts<T>>;
+    KRef k = consts<T>(sd);
     const int nx = sd->nx, ny = sd->ny;
     const uint32_t node_base = sd->node_base;
     const int64_t ushape_off = sd->ushape_off;
@@ -437,23 +442,19 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         } else {
             // f: phase field (App. C).  Stored result = the node's own zeroth
             // moment (storage units) + P^-1 of the raw-moment deviation.
-            T r[9], s[9];
+            T r[9];
             {
                 const T k1 = (T(1) - k.omega_k) * (jfx[j] - ux * phi) + k.omega_k * k.M_phi * theta * nxv;
                 const T k2 = (T(1) - k.omega_k) * (jfy[j] - uy * phi) + k.omega_k * k.M_phi * theta * nyv;
                 scalar_post_dev<T, MOV>(phi, k1, k2, ux, uy, r);
-                pinv_dev(r, k.scale_f, s);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) qf[j][q] = phn[j] + s[q];
+                pinv_dev_add(r, k.scale_f, phn[j], qf[j]);
             }
             // h: interface-bound surfactant (Sec. 3)
             {
                 const T k1 = (T(1) - k.omega_c) * (jhx[j] - ux * c) + k.omega_c * k.D_s * theta_c * nxv;
                 const T k2 = (T(1) - k.omega_c) * (jhy[j] - uy * c) + k.omega_c * k.D_s * theta_c * nyv;
                 scalar_post_dev<T, MOV>(c, k1, k2, ux, uy, r);
-                pinv_dev(r, k.scale_h, s);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) qh[j][q] = chn[j] + s[q];
+                pinv_dev_add(r, k.scale_h, chn[j], qh[j]);
             }
             // g: two-fluid flow (App. D)
             if constexpr (CPL) {
@@ -462,9 +463,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 flow_collide(mg[j], ux, uy, dP, psi, P_hat, fpx, fpy, ftx, fty, gam,
                              k.omega_zeta, omega_nu, t);
                 flow_post_raw(t, ux, uy, k.P_ref, r);
-                pinv_dev(r, k.scale_g, s);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) qg[j][q] = s[q];
+                pinv_dev(r, k.scale_g, qg[j]);
             }
             if (valid) {
                 const int own = gy * nx + gx;

@@ -182,6 +182,25 @@ __device__ __forceinline__ void pinv_dev(const T r[9], T scale, T s[9]) {
     s[7] = (p56 - r[6] - r[7]) * c5;
     s[8] = (m56 - r[6] + r[7]) * c5;
 }
+// the same added to base (the node's zeroth moment in storage units), in
+// one expression per value so that each is a single multiply-add
+template <class T>
+__device__ __forceinline__ void pinv_dev_add(const T r[9], T scale, T base, T s[9]) {
+    const T c0 = scale * T(2.25);
+    const T c1 = scale * T(4.5);
+    const T c5 = scale * T(9);
+    const T r37 = r[3] - r[8], r48 = r[4] - r[8];
+    s[0] = base + (r[0] - r[3] - r[4] + r[8]) * c0;
+    s[1] = base + (r[1] + r37 - r[7]) * c1;
+    s[2] = base + (r[2] + r48 - r[6]) * c1;
+    s[3] = base + (-r[1] + r37 + r[7]) * c1;
+    s[4] = base + (-r[2] + r48 + r[6]) * c1;
+    const T p56 = r[5] + r[8], m56 = r[8] - r[5];
+    s[5] = base + (p56 + r[6] + r[7]) * c5;
+    s[6] = base + (m56 + r[6] - r[7]) * c5;
+    s[7] = base + (p56 - r[6] - r[7]) * c5;
+    s[8] = base + (m56 - r[6] + r[7]) * c5;
+}
 
 // Scalar lattices f, h: deviation of the post-collision raw moments
 // F^-1(u) kappa~ from the rest moments s (1, 0, 0, cs2, cs2, 0, 0, 0, cs2^2),
