@@ -65,7 +65,7 @@ def test_init_populations3(oracle_mod, gpu_lib, name):
 PARITY3 = [("static3", "fp64"), ("static3", "fp32"), ("prescribed3", "fp64"),
            ("prescribed3", "fp32"), ("coupled3", "fp64"), ("coupled3", "fp32"),
            ("density3", "fp64"), ("shear3", "fp64"), ("shear3", "fp32"),
-           ("static3", "fp16"), ("shear3", "fp16")]
+           ("static3", "fp16"), ("shear3", "fp16"), ("thin3", "fp64"), ("thin3", "fp32")]
 
 
 @pytest.mark.parametrize("name,prec", PARITY3)
