@@ -209,3 +209,52 @@ def test_shear_wave_3d_decays_at_the_shear_viscosity(oracle_mod):
     assert abs(measured / (nu * k * k) - 1) < 5e-3, measured / (nu * k * k)
     # no transverse flow beyond the O(A^2) compressibility level
     assert np.abs(f["uz"]).max() < 1e-8 and np.abs(f["uy"]).max() < 1e-8
+
+
+@pytest.mark.parametrize("kv", [(1, 0, 0), (1, 2, 1), (0, 1, 3)])
+def test_scalar_step_fourier_mode_exact3(oracle_mod, kv):
+    """The 3D form of the exact advection-diffusion pin: with phi = 0 (exact
+    zero gradient, hence n = 0) the h lattice is linear; M(k) = diag(exp(-i k.e_a)) C(u) is built here from
+    the definitions (central moments by the definition sum over exponents
+    0..2 per axis, first order relaxed at omega, all others set to
+    c prod_i c(a_i), a dense 27x27 solve back).  Started on the least damped
+    eigenvector of M(k), the oracle reproduces lambda^n to rounding on a 6^3
+    periodic grid."""
+    import itertools
+    n, u, D, steps, amp, c0 = 6, (0.04, -0.03, 0.02), 0.05, 12, 0.01, 0.2
+    ex, ey, ez = oracle_mod.directions3()
+    dirs = (ex, ey, ez)
+    k = tuple(2 * np.pi * kk / n for kk in kv)
+    expo = list(itertools.product(range(3), repeat=3))
+    T = np.array([[np.prod([(dirs[d][a] - u[d]) ** e[d] for d in range(3)]) for a in range(27)]
+                  for e in expo])
+    om = 1.0 / (D / CS2 + 0.5)
+    cvec = (1.0, 0.0, CS2)
+    eq = np.array([np.prod([cvec[x] for x in e]) for e in expo])
+    E = np.zeros((27, 27))
+    for m, e in enumerate(expo):
+        if sum(e) == 1:
+            E[m, m] = 1.0 - om
+        else:
+            E[m, 0] = eq[m]
+    C = np.linalg.solve(T, E @ T)
+    M = np.diag(np.exp(-1j * (k[0] * ex + k[1] * ey + k[2] * ez))) @ C
+    lam, V = np.linalg.eig(M)
+    i = int(np.argmax(np.abs(lam)))
+    v = V[:, i]
+    heq = np.linalg.solve(T, c0 * eq)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    phase = np.exp(1j * (k[0] * x + k[1] * y + k[2] * z))
+    h0 = heq[:, None, None, None] + amp * np.real(v[:, None, None, None] * phase[None])
+    p = W.params3(nx=n, ny=n, nz=n, flow="prescribed", D_s=D, M_phi=0.1)
+    P = oracle_mod.make_params3(**p)
+    ones = np.ones((n, n, n))
+    us = [ones * u[0], ones * u[1], ones * u[2]]
+    base = oracle_mod.OracleSim3(P, 0 * ones, ones * c0, *us)
+    s = oracle_mod.OracleSim3.from_populations(P, base.f, h0, ushape=np.stack(us))
+    assert s.run(steps) == 0
+    expect = heq[:, None, None, None] + amp * np.real(lam[i] ** steps * v[:, None, None, None]
+                                                      * phase[None])
+    assert np.abs(s.h - expect).max() <= 1e-13 * np.abs(expect).max()
+    kk = sum(kc * kc for kc in k)
+    assert abs(abs(lam[i]) / math.exp(-D * kk) - 1) < 0.05 * kk

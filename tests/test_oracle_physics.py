@@ -191,3 +191,76 @@ def test_wall_ghost_normal_mirrors(oracle_mod):
             for k in ("curv", "fsx", "fsy", "nx", "ny"):
                 assert abs(dw[k] - dp[k]) <= 1e-13 * max(1.0, abs(dp[k])), (x, row, k)
             assert abs(dp["curv"]) > 1e-3
+
+
+CS2 = 1.0 / 3.0
+
+
+def _linear_scalar_step(dirs, u, D, k):
+    """M(k) = diag(exp(-i k.e_a)) C(u) of a scalar lattice without interface
+    flux, built here from the definitions: central moments about u by the
+    definition sum over exponents 0..2 per axis, the first-order moments
+    relaxed at omega = 1/(D/cs2 + 1/2), all others set to the equilibrium
+    c prod_i c(a_i) (c = (1, 0, cs2), c the zeroth moment), back to
+    populations by a dense solve.  Returns M(k), T and the equilibrium
+    moment vector per unit c."""
+    import itertools
+    dim = len(dirs)
+    q = len(dirs[0])
+    expo = list(itertools.product(range(3), repeat=dim))
+    T = np.array([[np.prod([(dirs[d][a] - u[d]) ** e[d] for d in range(dim)]) for a in range(q)]
+                  for e in expo])
+    om = 1.0 / (D / CS2 + 0.5)
+    cvec = (1.0, 0.0, CS2)
+    eq = np.array([np.prod([cvec[x] for x in e]) for e in expo])
+    E = np.zeros((q, q))
+    for m, e in enumerate(expo):
+        if sum(e) == 1:
+            E[m, m] = 1.0 - om
+        else:
+            E[m, 0] = eq[m]
+    C = np.linalg.solve(T, E @ T)
+    S = np.diag(np.exp(-1j * sum(k[d] * np.asarray(dirs[d]) for d in range(dim))))
+    return S @ C, T, eq
+
+
+@pytest.mark.parametrize("kx,ky", [(1, 0), (1, 2), (3, 1)])
+def test_scalar_step_fourier_mode_exact(oracle_mod, kx, ky):
+    """phi = 0 everywhere: every stencil term is an exact zero, so grad phi = 0,
+    n = 0 and the confining flux drops out (with phi = 1 the weighted sum of
+    equal values may leave a rounding residue, which the regularised normal
+    turns into an O(1e-5) direction).  h is then the
+    linear central-moment advection-diffusion scheme (Sec. 3, J = 0) under a
+    uniform prescribed u.  One step maps a Fourier mode v exp(i k.x) of the
+    populations to M(k) v exp(i k.x), with M(k) built here from the
+    definitions (_linear_scalar_step).  Started on the least damped
+    eigenvector of M(k) over a uniform equilibrium background, the oracle
+    must reproduce lambda^n to rounding on an 8x8 periodic grid."""
+    n, ux, uy, D, steps, amp, c0 = 8, 0.05, -0.03, 0.05, 25, 0.01, 0.2
+    ex, ey = oracle_mod.directions()
+    k = (2 * np.pi * kx / n, 2 * np.pi * ky / n)
+    M, T, eq = _linear_scalar_step((ex, ey), (ux, uy), D, k)
+    lam, V = np.linalg.eig(M)
+    i = int(np.argmax(np.abs(lam)))
+    v = V[:, i]
+    heq = np.linalg.solve(T, c0 * eq)
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    phase = np.exp(1j * (k[0] * x + k[1] * y))
+    h0 = heq[:, None, None] + amp * np.real(v[:, None, None] * phase[None])
+    p = W.params(nx=n, ny=n, flow="prescribed", D_s=D, M_phi=0.1)
+    P = oracle_mod.make_params(**p)
+    U, V_ = np.full((n, n), ux), np.full((n, n), uy)
+    base = oracle_mod.OracleSim(P, np.zeros((n, n)), np.full((n, n), c0), U, V_)
+    s = oracle_mod.OracleSim.from_populations(P, base.f, h0, ux_shape=U, uy_shape=V_)
+    assert s.run(steps) == 0
+    expect = heq[:, None, None] + amp * np.real(lam[i] ** steps * v[:, None, None] * phase[None])
+    assert np.abs(s.h - expect).max() <= 1e-13 * np.abs(expect).max()
+    # the mode is the diffusive one: |lambda| ~ exp(-D |k|^2), phase ~ -k.u
+    kk = k[0] ** 2 + k[1] ** 2
+    assert abs(abs(lam[i]) / math.exp(-D * kk) - 1) < 0.05 * kk
+    # the check sees a 0.1% error in the relaxation rate
+    Pw = oracle_mod.make_params(**dict(p, D_s=D * 1.001))
+    sw = oracle_mod.OracleSim.from_populations(Pw, base.f, h0, ux_shape=U, uy_shape=V_)
+    sw.run(steps)
+    assert np.abs(sw.h - expect).max() > 1e-9 * np.abs(expect).max()
