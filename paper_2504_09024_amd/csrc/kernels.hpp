@@ -233,7 +233,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const char* srcb = static_cast<const char*>(a.src) + sd->off * SB;
     const __amdgpu_buffer_rsrc_t rF = make_rsrc(srcb, lb);
     const __amdgpu_buffer_rsrc_t rH = make_rsrc(srcb + lb, lb);
-    const __amdgpu_buffer_rsrc_t rG = make_rsrc(srcb + (CPL ? 2 * lb : 0), lb);
+    const __amdgpu_buffer_rsrc_t rG = make_rsrc(srcb + (CPL ? 2 * (int64_t)lb : 0), lb);
     const int64_t step = *a.step_in;
     // tile, its radius-2 halo and their pull sources inside the grid: no
     // wrapping, no walls
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     char* dstb = static_cast<char*>(a.dst) + sd->off * SB;
     const __amdgpu_buffer_rsrc_t wF = make_rsrc(dstb, lb);
     const __amdgpu_buffer_rsrc_t wH = make_rsrc(dstb + lb, lb);
-    const __amdgpu_buffer_rsrc_t wG = make_rsrc(dstb + (CPL ? 2 * lb : 0), lb);
+    const __amdgpu_buffer_rsrc_t wG = make_rsrc(dstb + (CPL ? 2 * (int64_t)lb : 0), lb);
     const bool urho = sd->uniform_rho, unu = sd->uniform_nu;
     const uint32_t step_key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
     int fault = 0;
@@ -567,9 +567,10 @@ __global__ __launch_bounds__(WG) void k_init(const InitArgs a) {
     for (int q = 0; q < 9; ++q) {
         int pq, node;
         pull_slot(x, y, q, nx, ny, a.walls != 0, pq, node);
-        pop[pq * plane + node] = S(phin + sf[q]);
-        pop[(9 + pq) * plane + node] = S(chn + sh[q]);
-        if (cpl) pop[(18 + pq) * plane + node] = S(sg[q]);
+        // 64-bit: 26 planes of the largest FP16 lattice exceed 2^31 elements
+        pop[(int64_t)pq * plane + node] = S(phin + sf[q]);
+        pop[(int64_t)(9 + pq) * plane + node] = S(chn + sh[q]);
+        if (cpl) pop[(int64_t)(18 + pq) * plane + node] = S(sg[q]);
     }
     if (a.flow == FLOW_PRESCRIBED && a.ushape) {
         T* us = static_cast<T*>(a.ushape);
@@ -638,8 +639,8 @@ __global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const Si
         double vf = 0.0, vh = 0.0;
         for (int q = 0; q < 9; ++q) {
             const double w = wgt<double>(q);
-            vf += w * (double(p[q * plane + i]) * inv_f + qref);
-            vh += w * (double(p[(9 + q) * plane + i]) * inv_h);
+            vf += w * (double(p[(int64_t)q * plane + i]) * inv_f + qref);
+            vh += w * (double(p[(int64_t)(9 + q) * plane + i]) * inv_h);
         }
         sf += vf;
         sh += vh;

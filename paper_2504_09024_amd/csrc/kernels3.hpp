@@ -245,7 +245,7 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
     scalar_moments27(v, hm[0], hm[1], hm[2], hm[3]);
     T r0 = T(0), r1[3] = {T(0), T(0), T(0)}, r2[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if constexpr (CPL) {
-        pull27<S, T, WALLS>(make_rsrc(srcb + 2 * lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+        pull27<S, T, WALLS>(make_rsrc(srcb + 2 * (int64_t)lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
         // deviations d_a = w_a s_a / scale and their raw moments
         {
 #pragma clang fp contract(off)
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                             wcorr = -T(2) * rho * k.u_wall * k.scale_g;
                         }
                     }
-                    const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + 2 * lb, lb);
+                    const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + 2 * (int64_t)lb, lb);
 #pragma unroll
                     for (int q = 0; q < 27; ++q) {
                         T v = k.scale_g * t[q] * inv_wgt3<T>(q);

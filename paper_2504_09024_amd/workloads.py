@@ -33,6 +33,13 @@ BASE_PARAMS = dict(
 )
 
 
+def _sech2(s):
+    """sech^2 s = 4 e^{-2|s|} / (1 + e^{-2|s|})^2, without overflow far from
+    the interface."""
+    e = np.exp(-2.0 * np.abs(s))
+    return 4.0 * e / (1.0 + e) ** 2
+
+
 def params(**kw) -> dict:
     p = dict(BASE_PARAMS)
     p.update(kw)
@@ -61,7 +68,7 @@ def drop_fields(nx, ny, xc, yc, R, W, c_hat=None, phi_a=1.0, phi_b=0.0, y_offset
         ch = c_hat(theta)
     else:
         ch = np.full_like(phi, float(c_hat))
-    c = ch / np.cosh(2.0 * zeta / W) ** 2
+    c = ch * _sech2(2.0 * zeta / W)
     return np.ascontiguousarray(phi), np.ascontiguousarray(c)
 
 
@@ -180,7 +187,7 @@ def flat_interface(nx=64, ny=8, W=4.0, c_hat=0.0, M_phi=0.1, D_s=0.05):
     x1, x2 = nx / 4.0, 3.0 * nx / 4.0
     zeta = np.minimum(x - x1, x2 - x)
     phi = 0.5 + 0.5 * np.tanh(2.0 * zeta / W)
-    c = c_hat / np.cosh(2.0 * zeta / W) ** 2
+    c = c_hat * _sech2(2.0 * zeta / W)
     p = params(nx=nx, ny=ny, bc_y="periodic", flow="none", W=W, M_phi=M_phi, D_s=D_s)
     return p, dict(phi=np.ascontiguousarray(np.broadcast_to(phi, (ny, nx))),
                    c=np.ascontiguousarray(np.broadcast_to(c, (ny, nx))))
@@ -254,7 +261,7 @@ def drop_fields3(nx, ny, nz, xc, yc, zc, R, W, c_hat=None, phi_a=1.0, phi_b=0.0,
         ch = c_hat(np.where(r > 0, x / np.where(r > 0, r, 1.0), 0.0))
     else:
         ch = np.full_like(phi, float(c_hat))
-    c = ch / np.cosh(2.0 * zeta / W) ** 2
+    c = ch * _sech2(2.0 * zeta / W)
     return np.ascontiguousarray(phi), np.ascontiguousarray(c)
 
 
