@@ -12,6 +12,21 @@ def _ragged():
     return p, dict(phi=phi, c=c)
 
 
+def _tiny(nx, ny, bc_y):
+    """Grids smaller than one tile (x and y halos wrap or mirror more than
+    once): smooth phase-shifted waves of every field, no node with a
+    vanishing gradient."""
+    p = W.params(nx=nx, ny=ny, bc_y=bc_y, flow="coupled", sigma0=1e-3, beta=0.2,
+                 u_wall=1e-2 if bc_y == "walls" else 0.0, M_phi=0.04, D_s=0.02)
+    x = (np.arange(nx)[None, :] + 0.31) * 2 * np.pi / nx
+    y = (np.arange(ny)[:, None] + 0.17) * 2 * np.pi / ny
+    phi = 0.5 + 0.3 * np.sin(x + 0.7) * np.cos(y - 0.4) + 0.1 * np.cos(2 * x + y)
+    c = 0.2 + 0.05 * np.cos(x - 0.2) * np.sin(y + 0.9)
+    ux = 1e-2 * np.sin(y + 0.3) + 0 * x
+    uy = 1e-2 * np.cos(x + 0.5) + 0 * y
+    return p, dict(phi=phi, c=c, ux=ux, uy=uy)
+
+
 CASES = {
     # static drop of Sec. 4.1 at the 128x128 scale, all 2000 steps
     "c1_static_drop": (lambda: W.static_drop(), 2000),
@@ -37,9 +52,14 @@ CASES = {
     # differences about 2.3x per step (the oracle turns a 1e-16 perturbation
     # into 3e-12 after 10 steps and 7e-8 after 60)
     "c2_full": (lambda: W.vortex_drop(center=(256.3, 383.6)), 4),
+    # grids smaller than one tile: the minimum 4 x 4 (periodic; 5 steps: the
+    # velocity decays ~25% per step in a 4-wide box, and its relative
+    # rounding floor with it) and 5 x 6 with walls
+    "tiny_periodic": (lambda: _tiny(4, 4, "periodic"), 5),
+    "tiny_walls": (lambda: _tiny(5, 6, "walls"), 50),
 }
 
 # cases compared against the FP64 bar (1e-12) and cheap enough for the CPU
 # conditioning check
 FP64_CONDITIONING = ["ragged_periodic", "vortex", "shear_drop", "coupled_random",
-                     "density_ratio", "c3_full", "c2_full"]
+                     "density_ratio", "c3_full", "c2_full", "tiny_periodic", "tiny_walls"]

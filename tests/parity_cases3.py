@@ -13,6 +13,9 @@ CASES3 = {
                                           rho_a=2.0, rho_b=1.0, nu_a=0.05, nu_b=0.1,
                                           omega_zeta=0.9, F_ext_x=1e-5, F_ext_y=-2e-5,
                                           F_ext_z=3e-5, bc_y="periodic"), 40),
+    # the smallest grid: 4 x 4 x 1, every halo wraps or mirrors more than once
+    "tiny3": (lambda: W.random_fields3(4, 4, 1, seed=7, amp=0.3, sigma0=1e-3, beta=0.2,
+                                       u_wall=1e-2, M_phi=0.04, D_s=0.02), 10),
     # two planes: every z stencil wraps onto the same two planes
     "thin3": (lambda: W.random_fields3(40, 12, 2, seed=6, amp=1.0, sigma0=1e-3, beta=0.2,
                                        u_wall=1e-2, M_phi=0.04, D_s=0.02), 30),

@@ -68,6 +68,7 @@ PARITY = [
     ("coupled_random", "fp64"),
     ("density_ratio", "fp64"),
     ("c2_full", "fp64"), ("c2_full", "fp32"),
+    ("tiny_periodic", "fp64"), ("tiny_walls", "fp64"), ("tiny_walls", "fp32"),
 ]
 
 
@@ -252,6 +253,19 @@ def test_graph_matches_direct_launch(gpu_lib, prec):
         ctx.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+def test_zero_steps(gpu_lib):
+    """step(0) launches nothing: populations and the step count unchanged."""
+    p, fl = W.shear_drop(nx=192, ny=64, R=10.0)
+    ctx = gpu_ctx(p, fl, "fp32")
+    ctx.step(3)
+    before = ctx.get_populations(0)
+    ctx.step(0)
+    assert ctx.step_count == 3
+    for a, b in zip(before, ctx.get_populations(0)):
+        assert np.array_equal(a, b)
+    ctx.close()
 
 
 def test_batched_matches_single_bitwise(gpu_lib):

@@ -65,7 +65,8 @@ def test_init_populations3(oracle_mod, gpu_lib, name):
 PARITY3 = [("static3", "fp64"), ("static3", "fp32"), ("prescribed3", "fp64"),
            ("prescribed3", "fp32"), ("coupled3", "fp64"), ("coupled3", "fp32"),
            ("density3", "fp64"), ("shear3", "fp64"), ("shear3", "fp32"),
-           ("static3", "fp16"), ("shear3", "fp16"), ("thin3", "fp64"), ("thin3", "fp32")]
+           ("static3", "fp16"), ("shear3", "fp16"), ("thin3", "fp64"), ("thin3", "fp32"),
+           ("tiny3", "fp64"), ("tiny3", "fp32")]
 
 
 @pytest.mark.parametrize("name,prec", PARITY3)
@@ -121,6 +122,19 @@ def test_store_policies_bitwise3(gpu_lib):
         c.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_zero_steps3(gpu_lib):
+    """step(0) launches nothing: populations and the step count unchanged."""
+    p, fl = CASES3["coupled3"][0]()
+    c = ctx3(p, fl, "fp32")
+    c.step(3)
+    before = c.get_populations(0)
+    c.step(0)
+    assert c.step_count == 3
+    for a, b in zip(before, c.get_populations(0)):
+        assert np.array_equal(a, b)
+    c.close()
 
 
 def test_graph_matches_direct3(gpu_lib):
