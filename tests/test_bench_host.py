@@ -77,3 +77,29 @@ def test_record_traffic_sums_the_3d_step_kernels(tmp_path):
     assert ent["algorithmic_bytes"] == 3 * 27 * 2 * 4 * 100
     assert ent["per_kernel"]["k_collide3"]["write_bytes"] == 80 * 1024
     assert json.loads(out.read_text())["c5:fp32"]["kernel_hash"] == bench.kernel_hash(3)
+
+
+def test_bench_refuses_several_gpus():
+    """One GPU only: --gpus 2 exits with status 2 and says why."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libcmlb.so the binding raises; there is no CPU fallback."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2504_09024_amd import cmlb\n"
+            "try:\n"
+            "    cmlb.load(%r)\n"
+            "except RuntimeError as e:\n"
+            "    print('raised:', e)\n"
+            "    sys.exit(3)\n") % (ROOT, str(tmp_path / "libcmlb.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 3, r.stdout + r.stderr
+    assert "no CPU fallback" in r.stdout
