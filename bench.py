@@ -220,7 +220,47 @@ def cpu_baseline(sims, target_s=12.0):
                       f"{p.get('flow', 'coupled')}, {dt:.1f} s, FP64, OpenMP over rows)"}
 
 
-WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2", "c5")
+def oracle_leg(name, min_s=2.0):
+    """Time the FP64 oracle on one configuration (C1 static drop 128^2,
+    2 lattices; C3 coupled drop 1024x512) with the OpenMP threads this process
+    was started with: at least two steps and about min_s seconds."""
+    import oracle
+    from paper_2504_09024_amd import workloads as W
+    p, fl = W.static_drop() if name == "c1" else W.shear_drop()
+    o = oracle.OracleSim(oracle.make_params(**p), fl["phi"], fl["c"], fl.get("ux"), fl.get("uy"))
+    steps, dt = 0, 0.0
+    while steps < 2 or dt < min_s:
+        t0 = time.perf_counter()
+        o.run(1 if steps < 2 else max(1, steps))
+        dt += time.perf_counter() - t0
+        steps += 1 if steps < 2 else max(1, steps)
+    return {"config": name, "threads": oracle.num_threads(), "steps": steps,
+            "MLUPS": round(p["nx"] * p["ny"] * steps / dt / 1e6, 3)}
+
+
+def oracle_timing():
+    """The oracle on C1 and C3, single-threaded and on every core this
+    process may use; one JSON line with the host's CPU model."""
+    import subprocess
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    legs = []
+    for name in ("c1", "c3"):
+        for threads in (1, cores):
+            env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-leg", name],
+                               env=env, capture_output=True, text=True, check=True)
+            legs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+            log(f"[bench] oracle {legs[-1]}")
+    print(json.dumps({"oracle_timing": legs, "cpu_model": model, "cores": cores}), flush=True)
+
+
+WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2", "c5", "calib")
 # storage forms reported beside the headline: the batch, the single
 # 1024x512 drop and the 3D drop
 FORM_WORKLOADS = ("batched", "c3", "c5")
@@ -251,6 +291,11 @@ def workload(W, name):
         sims = [W.shear_drop3()]
         desc = ("3D (D3Q27) coupled surfactant-laden drop in shear, 256x128x128, R=32, Ca=0.3, "
                 "E=0.2, c0/c_max=0.3, Re=0.1, walls at +-U0; moments and collision launches")
+    elif name == "calib":
+        sims = [W.shear_drop(nx=4096, ny=2048)]
+        desc = ("roofline calibration: one coupled surfactant-laden shear drop, 4096x2048, "
+                "R=256, Ca=0.3, E=0.2, c0/c_max=0.3, Re=0.1, walls at +-U0 (0.9 GB per FP32 "
+                "copy of the populations)")
     elif name == "e2":
         sims = [W.advected_drop()]
         desc = ("drop in a uniform flow (Sec. 4.2), 1024x512 periodic, R=128, D_s=0.1, "
@@ -300,7 +345,17 @@ def main():
                     help="(no GPU) turn rocprofv3 counter_collection.csv files of the step "
                          "kernel (--workload/--precision) and of the copy calibration into "
                          "profiles/traffic.json")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="(no GPU) time the FP64 CPU oracle on C1 and C3, 1 thread and all cores")
+    ap.add_argument("--oracle-leg", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.oracle_leg:
+        print(json.dumps(oracle_leg(args.oracle_leg)), flush=True)
+        return
+    if args.oracle_timing:
+        oracle_timing()
+        return
 
     if args.record_traffic:
         from paper_2504_09024_amd import workloads as W
