@@ -7,6 +7,8 @@ beyond the oracle's reach).
 * Sec. 4.2: the same drop on a 1024 x 512 box carried by a uniform flow
   over Lo = 512 columns in T_D = R^2/D_s steps: profile about the shifted
   centre, and phi against the initial drop moved by 512 columns.
+* 3D: the steady Taylor deformation of a clean drop in shear against
+  35/32 Ca, and its growth with confinement.
 * Single vortex (512 x 512, R = 64, U0 = 0.02, T = 20000): after the full
   reversal period the drop returns; one step deep in the run against the
   oracle at full size.
@@ -153,3 +155,51 @@ def test_shear_drop_deformation_paper_scale(gpu_lib):
     slope = [d4[i] / ca for i, ca in enumerate(Cas)]
     assert max(slope) / min(slope) < 1.05, slope                     # linear regime
     ctx.close()
+
+
+def test_taylor_deformation_3d(gpu_lib):
+    """3D (D3Q27) clean drop in simple shear at small Ca, Re = 0.1: the steady
+    Taylor deformation D of the phi = 1/2 contour in the shear plane.
+    Taylor's small-deformation result for equal viscosities is
+    D = (19 + 16)/(16 + 16) Ca = 35/32 Ca; the W = 4 interface carries an
+    effective tension of ~0.94 sigma0 (the 3D Laplace test), so the
+    unconfined expectation is D/Ca ~ 1.17.  With walls at 2R/H = 0.2 and
+    periodic images (8R apart in x, 5R in z) the measured D/Ca must lie
+    within [1.0, 1.2] of that; D is steady (gdot t = 3 against 4), linear in
+    Ca (0.1 against 0.05), and grows with confinement (2R/H = 0.4)."""
+    from profile_util import taylor_deformation
+
+    def run(R, Ca, nx, ny, nz):
+        p, fl = W.shear_drop3(nx=nx, ny=ny, nz=nz, R=R, Ca=Ca, E=0.0, c0=0.0, Re=0.1)
+        gdot = 0.1 * 0.1 / (R * R)
+        ctx = cmlb_ctx3(p, fl)
+        out, done = [], 0
+        for g in (3.0, 4.0):
+            n = int(round(g / gdot))
+            ctx.step(n - done)
+            done = n
+            out.append(taylor_deformation(ctx.read_fields(0)["phi"][nz // 2], nx / 2.0,
+                                          ny / 2.0 - 0.5))
+        assert ctx.fault_flags(0) == 0
+        ctx.close()
+        print(f"3D Taylor R={R} Ca={Ca} 2R/H={2 * R / ny:.2f}: D={out[1]:.4f} "
+              f"D/Ca={out[1] / Ca:.3f} (35/32 = {35 / 32:.3f})", flush=True)
+        return out
+
+    d1 = run(16.0, 0.1, 128, 160, 80)
+    d2 = run(16.0, 0.05, 128, 160, 80)
+    for d in (d1, d2):
+        assert abs(d[1] - d[0]) < 0.01 * d[1]                      # steady
+    assert abs(d1[1] / (2 * d2[1]) - 1) < 0.05                     # linear in Ca
+    ratio = (d1[1] / 0.1) / (35 / 32 / 0.94)
+    assert 1.0 < ratio < 1.2, ratio
+    dw = run(12.0, 0.1, 96, 120, 64)
+    dn = run(12.0, 0.1, 96, 60, 64)
+    assert dn[1] > 1.05 * dw[1]                                     # confinement raises D
+
+
+def cmlb_ctx3(p, fl):
+    from paper_2504_09024_amd import cmlb
+    ctx = cmlb.Context3(p, "fp32")
+    ctx.init_fields(0, fl["phi"], fl["c"], fl["ux"], fl["uy"], fl["uz"])
+    return ctx
