@@ -166,11 +166,12 @@ def test_taylor_deformation_3d(gpu_lib):
     unconfined expectation is D/Ca ~ 1.17.  With walls at 2R/H = 0.2 and
     periodic images (8R apart in x, 5R in z) the measured D/Ca must lie
     within [1.0, 1.2] of that; D is steady (gdot t = 3 against 4), linear in
-    Ca (0.1 against 0.05), and grows with confinement (2R/H = 0.4)."""
+    Ca (0.1 against 0.05), grows with confinement (2R/H = 0.4), and grows
+    with surfactant (beta = 0.25, c0 = 0.3, Pe_s = 1), as in Sec. 4.3."""
     from profile_util import taylor_deformation
 
-    def run(R, Ca, nx, ny, nz):
-        p, fl = W.shear_drop3(nx=nx, ny=ny, nz=nz, R=R, Ca=Ca, E=0.0, c0=0.0, Re=0.1)
+    def run(R, Ca, nx, ny, nz, E=0.0, c0=0.0):
+        p, fl = W.shear_drop3(nx=nx, ny=ny, nz=nz, R=R, Ca=Ca, E=E, c0=c0, Re=0.1)
         gdot = 0.1 * 0.1 / (R * R)
         ctx = cmlb_ctx3(p, fl)
         out, done = [], 0
@@ -182,7 +183,7 @@ def test_taylor_deformation_3d(gpu_lib):
                                           ny / 2.0 - 0.5))
         assert ctx.fault_flags(0) == 0
         ctx.close()
-        print(f"3D Taylor R={R} Ca={Ca} 2R/H={2 * R / ny:.2f}: D={out[1]:.4f} "
+        print(f"3D Taylor R={R} Ca={Ca} 2R/H={2 * R / ny:.2f} beta={E}: D={out[1]:.4f} "
               f"D/Ca={out[1] / Ca:.3f} (35/32 = {35 / 32:.3f})", flush=True)
         return out
 
@@ -196,6 +197,8 @@ def test_taylor_deformation_3d(gpu_lib):
     dw = run(12.0, 0.1, 96, 120, 64)
     dn = run(12.0, 0.1, 96, 60, 64)
     assert dn[1] > 1.05 * dw[1]                                     # confinement raises D
+    ds = run(12.0, 0.1, 96, 120, 64, E=0.25, c0=0.3)
+    assert ds[1] > 1.05 * dw[1]                                     # surfactant raises D
 
 
 def cmlb_ctx3(p, fl):
