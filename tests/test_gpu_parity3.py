@@ -3,8 +3,9 @@ the C ABI of include/cmlb3.h.
 
 Tolerances (relative L2 per field at the final step): FP64 <= 1e-12,
 FP32 <= 1e-5 on phi, c, u, FP16 storage <= 1e-3.  Sizes span several
-64 x 4 x 2 collision tiles and 64 x 4-row moment tiles with ragged tails in
-x, y and z; the FP64 cases are checked to be well conditioned on the CPU.
+collision columns (64 x 4 or 64 x 8 nodes, one to three z segments) and
+64 x 4-row moment tiles with ragged tails in x, y and z, down to a 4 x 4 x 1
+grid; the FP64 cases are checked to be well conditioned on the CPU.
 """
 import math
 
