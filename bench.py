@@ -337,6 +337,8 @@ def main():
                     help="keep the library's default launch shape instead of timing the options")
     ap.add_argument("--no-forms", action="store_true", help="skip the other storage forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-bw", default="", metavar="MIB,MIB,...",
+                    help="only time torch device copies of these sizes (GB/s read + write)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -385,6 +387,28 @@ def main():
     tstream = torch.cuda.Stream()
     torch.cuda.set_stream(tstream)
     stream = tstream.cuda_stream
+
+    if args.copy_bw:
+        # device-to-device copy bandwidth (read + write bytes) at working
+        # sets matching the workloads: context for their roofline fractions
+        out = {}
+        for mib in [int(v) for v in args.copy_bw.split(",")]:
+            n = mib * (1 << 20) // 4
+            a = torch.ones(n, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(5, min(200, (8 << 30) // (2 * 4 * n)))
+            e0.record()
+            for _ in range(reps):
+                b.copy_(a)
+            e1.record()
+            torch.cuda.synchronize()
+            out[f"{mib}MiB"] = round(2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+            del a, b
+        print(json.dumps({"copy_GBps_read_plus_write": out}), flush=True)
+        return
 
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 4
