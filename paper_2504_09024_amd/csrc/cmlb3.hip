@@ -81,6 +81,12 @@ void fill3(Consts3<T>& k, const cmlb3_sim_params& p, const Desc3& d, int walls) 
     k.Fz = T(p.F_ext_z);
     k.P_ref = T(d.P_ref);
     k.dr_cs2 = T((p.rho_a - p.rho_b) / dphi / 3.0);
+    for (int n = 0; n < 4; ++n) {
+        // 1/w_a / 2^n = (27/8) 2^n, times the power-of-two storage scale
+        k.enc_f[n] = T(d.scale_f * 3.375 * (1 << n));
+        k.enc_h[n] = T(d.scale_h * 3.375 * (1 << n));
+        k.enc_g[n] = T(d.scale_g * 3.375 * (1 << n));
+    }
 }
 
 }  // namespace

@@ -21,7 +21,12 @@ struct Store<_Float16> {
 // Storage access through buffer descriptors: one descriptor per lattice, the
 // node offset in a VGPR and the direction plane in the SGPR offset, so the 27
 // loads and stores of a node share one address computation.  Out-of-range
-// buffer accesses return 0 / are dropped by the hardware.
+// buffer accesses return 0 / are dropped by the hardware.  `load` returns
+// the stored value in the compute type; `raw` returns it as a register word
+// (binary16 zero-extended to 32 bits, one value per register) for `widen` to
+// convert later, after the branches that issue the loads, so that a wave's
+// loads stay in flight together (a conversion inside a branch waits for its
+// load before the branch ends).
 // ---------------------------------------------------------------------------
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
@@ -38,8 +43,13 @@ template <class S>
 struct Buf;
 template <>
 struct Buf<double> {
-    static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+    using word = double;
+    static __device__ __forceinline__ double widen(word w) { return w; }
+    static __device__ __forceinline__ double raw(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+        return raw(r, vo, so);
     }
     template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, double v,
@@ -49,8 +59,13 @@ struct Buf<double> {
 };
 template <>
 struct Buf<float> {
-    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+    using word = float;
+    static __device__ __forceinline__ float widen(word w) { return w; }
+    static __device__ __forceinline__ float raw(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+        return raw(r, vo, so);
     }
     template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
@@ -58,14 +73,22 @@ struct Buf<float> {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, vo, so, CP);
     }
 };
-// binary16 storage: loads widen exactly; stores round stochastically with
-// gfx950's v_cvt_sr_f16_f32 (the top 13 bits of the random word decide the
-// rounding direction; exactly representable values are kept).  Stochastic
+// binary16 storage: values widen exactly to FP32; stores round
+// stochastically with gfx950's v_cvt_sr_f16_f32 (the top 13 bits of the
+// random word decide the rounding direction; exactly representable values
+// are kept).  Stochastic
 // rounding keeps the per-step storage errors independent and unbiased, where
 // round-to-nearest would repeat the same error every step at a quasi-steady
 // node.
 template <>
 struct Buf<_Float16> {
+    using word = uint32_t;
+    static __device__ __forceinline__ float widen(word w) {
+        return float(__builtin_bit_cast(_Float16, (unsigned short)w));
+    }
+    static __device__ __forceinline__ word raw(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    }
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)));
     }

@@ -76,12 +76,6 @@ __device__ __forceinline__ constexpr T wgt3(int a) {
     const int n = (a % 3 != 0) + ((a / 3) % 3 != 0) + (a / 9 != 0);
     return n == 0 ? C3<T>::w0 : (n == 1 ? C3<T>::w1 : (n == 2 ? C3<T>::w2 : C3<T>::w3));
 }
-template <class T>
-__device__ __forceinline__ constexpr T inv_wgt3(int a) {
-    const int n = (a % 3 != 0) + ((a / 3) % 3 != 0) + (a / 9 != 0);
-    return n == 0 ? T(27) / T(8) : (n == 1 ? T(27) / T(2) : (n == 2 ? T(54) : T(216)));
-}
-
 // Per-simulation constants in the compute type.
 template <class T>
 struct Consts3 {
@@ -90,6 +84,10 @@ struct Consts3 {
     T M_phi, D_s, omega_k, omega_c;
     T rho_b, drho, nu_b, dnu, inv_rho_b, omega_nu_b, omega_zeta;
     T sigma0, beta, c_max, inv_cmax, ks, u_wall, Fx, Fy, Fz, P_ref, dr_cs2;
+    // storage encoding of a post-collision population with n non-zero
+    // direction components as left by inverse27: scale / w_a / 2^n (read by
+    // the binary16 kernels; FP32 and FP64 storage is unscaled)
+    T enc_f[4], enc_h[4], enc_g[4];
 };
 
 struct SimDev3 {
@@ -155,9 +153,11 @@ __device__ __forceinline__ int tile_index(const StepArgs3& a) {
 // ---------------------------------------------------------------------------
 constexpr int MT_ROWS = 4;  // (y, z) rows per moments tile
 
-template <class S, class T, bool WALLS>
+// stored values of the 27 pulled populations, as register words
+template <class S, bool WALLS>
 __device__ __forceinline__ void pull27(__amdgpu_buffer_rsrc_t r, int pb, int x, int y, int z,
-                                       int nx, int ny, int nz, bool inner, T v[27]) {
+                                       int nx, int ny, int nz, bool inner,
+                                       typename Buf<S>::word v[27]) {
     constexpr int SB = sizeof(S);
     const int plane = nx * ny;
     if (inner) {
@@ -165,7 +165,7 @@ __device__ __forceinline__ void pull27(__amdgpu_buffer_rsrc_t r, int pb, int x, 
 #pragma unroll
         for (int a = 0; a < 27; ++a) {
             const int so = a * pb - (EXd(a) + EYd(a) * nx + EZd(a) * plane) * SB;
-            v[a] = T(Buf<S>::load(r, vo, so));
+            v[a] = Buf<S>::raw(r, vo, so);
         }
         return;
     }
@@ -185,7 +185,7 @@ __device__ __forceinline__ void pull27(__amdgpu_buffer_rsrc_t r, int pb, int x, 
             }
         }
         // the plane varies per lane at a wall, so it goes into the vector offset
-        v[a] = T(Buf<S>::load(r, ((sz * ny + sy) * nx + sx) * SB + pa * pb, 0));
+        v[a] = Buf<S>::raw(r, ((sz * ny + sy) * nx + sx) * SB + pa * pb, 0);
     }
 }
 
@@ -236,16 +236,40 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
     const bool inner = x >= 1 && x + 1 < nx && y >= 1 && y + 1 < ny && z >= 1 && z + 1 < nz;
     T* mom = static_cast<T*>(a.mom) + sd->moff + ((z * ny + y) * nx + x);
     // all pulls before the first store: a load issued after a store would
-    // wait for that store as well
-    T v[27];
-    T fm[4], hm[4];
-    pull27<S, T, WALLS>(make_rsrc(srcb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+    // wait for that store as well.  Binary16 values are widened only after
+    // all three lattices' pulls have been issued: widening inside a pull's
+    // branch made a wave wait for one lattice's 27 loads before it issued
+    // the next 27 (with the 81 in flight the 256x128x128 drop steps 4.7%
+    // faster).  FP32 and FP64 need no widening, and the compiler already
+    // issues their 81 pulls ahead of the moment sums.
+    constexpr bool AHEAD = Store<S>::scaled;
+    using W = typename Buf<S>::word;
+    W sf[27], sh[AHEAD ? 27 : 1], sg[AHEAD && CPL ? 27 : 1];
+    T v[27], fm[4], hm[4];
+    pull27<S, WALLS>(make_rsrc(srcb, lb), pb, x, y, z, nx, ny, nz, inner, sf);
+    if constexpr (AHEAD) {
+        pull27<S, WALLS>(make_rsrc(srcb + lb, lb), pb, x, y, z, nx, ny, nz, inner, sh);
+        if constexpr (CPL)
+            pull27<S, WALLS>(make_rsrc(srcb + 2 * (int64_t)lb, lb), pb, x, y, z, nx, ny, nz, inner, sg);
+    }
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = T(Buf<S>::widen(sf[q]));
     scalar_moments27(v, fm[0], fm[1], fm[2], fm[3]);
-    pull27<S, T, WALLS>(make_rsrc(srcb + lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+    if constexpr (AHEAD) {
+#pragma unroll
+        for (int q = 0; q < 27; ++q) v[q] = T(Buf<S>::widen(sh[q]));
+    } else {
+        pull27<S, WALLS>(make_rsrc(srcb + lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+    }
     scalar_moments27(v, hm[0], hm[1], hm[2], hm[3]);
     T r0 = T(0), r1[3] = {T(0), T(0), T(0)}, r2[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if constexpr (CPL) {
-        pull27<S, T, WALLS>(make_rsrc(srcb + 2 * (int64_t)lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+        if constexpr (AHEAD) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) v[q] = T(Buf<S>::widen(sg[q]));
+        } else {
+            pull27<S, WALLS>(make_rsrc(srcb + 2 * (int64_t)lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
+        }
         // deviations d_a = w_a s_a / scale and their raw moments
         {
 #pragma clang fp contract(off)
@@ -285,18 +309,30 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
 
 // ---------------------------------------------------------------------------
 // Axis-wise inverse of the central-moment map.  t[i + 3j + 9k] holds central
-// moments with exponents (i, j, k) on entry and populations with components
-// (E1(i), E1(j), E1(k)) on exit.  One axis: central -> raw
-// (r0 = k0, r1 = k1 + u k0, r2 = k2 + 2u k1 + u^2 k0), raw -> populations
-// (q0 = r0 - r2, q+ = (r2 + r1)/2, q- = (r2 - r1)/2).
+// moments with exponents (i, j, k) on entry and, on exit, the populations
+// with components (E1(i), E1(j), E1(k)) times 2^n, n the number of non-zero
+// components.  One axis: central -> raw (r0 = k0, r1 = k1 + u k0,
+// r2 = k2 + 2u k1 + u^2 k0), raw -> populations (q0 = r0 - r2,
+// 2 q+ = r2 + r1, 2 q- = r2 - r1).  The halvings are left to the storage
+// encoding, which multiplies each population by a constant anyway
+// (enc_wgt3); scaling by powers of two is exact, so this changes no bits.
 // ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ void axis_inv(T& a0, T& a1, T& a2, T u, T u2) {
     const T r1 = a1 + u * a0;
     const T r2 = a2 + T(2) * u * a1 + u2 * a0;
     a0 = a0 - r2;
-    a1 = T(0.5) * (r2 + r1);
-    a2 = T(0.5) * (r2 - r1);
+    a1 = r2 + r1;
+    a2 = r2 - r1;
+}
+// number of non-zero components of direction a
+__device__ __forceinline__ constexpr int nnz3(int a) {
+    return (a % 3 != 0) + ((a / 3) % 3 != 0) + (a / 9 != 0);
+}
+// 1/w_a / 2^n for a direction with n non-zero components: (27/8) 2^n
+template <class T>
+__device__ __forceinline__ constexpr T enc_wgt3(int n) {
+    return T(27) / T(8) * T(1 << n);
 }
 template <class T>
 __device__ __forceinline__ void inverse27(T t[27], T ux, T uy, T uz) {
@@ -461,6 +497,22 @@ __device__ __forceinline__ void unit3(T gx, T gy, T gz, T n[3]) {
     n[0] = gx * inv;
     n[1] = gy * inv;
     n[2] = gz * inv;
+}
+
+// A population from inverse27 in storage units, t / w_a / 2^n times the
+// storage scale: binary16 takes the product from the simulation's constant
+// table; FP32 and FP64 storage is unscaled, so the factor is a literal.
+// encode3_add adds the result to base in the same expression (one
+// multiply-add).
+template <class S, class T>
+__device__ __forceinline__ T encode3(T t, const T tab[4], int q) {
+    if constexpr (Store<S>::scaled) return t * tab[nnz3(q)];
+    else return t * enc_wgt3<T>(nnz3(q));
+}
+template <class S, class T>
+__device__ __forceinline__ T encode3_add(T base, T t, const T tab[4], int q) {
+    if constexpr (Store<S>::scaled) return base + t * tab[nnz3(q)];
+    else return base + t * enc_wgt3<T>(nnz3(q));
 }
 
 // ---------------------------------------------------------------------------
@@ -790,7 +842,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
 #pragma unroll
                     for (int q = 0; q < 27; ++q)
                         Buf<S>::template store<CP>(w, vo, q * pb,
-                                                   m0 + k.scale_f * t[q] * inv_wgt3<T>(q),
+                                                   encode3_add<S>(m0, t[q], k.enc_f, q),
                                                    rs + weyl(3 * q));
                 }
                 // h: surfactant
@@ -805,7 +857,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
 #pragma unroll
                     for (int q = 0; q < 27; ++q)
                         Buf<S>::template store<CP>(w, vo, q * pb,
-                                                   m0 + k.scale_h * t[q] * inv_wgt3<T>(q),
+                                                   encode3_add<S>(m0, t[q], k.enc_h, q),
                                                    rs + weyl(3 * q + 1));
                 }
                 // g: flow
@@ -840,7 +892,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                     const __amdgpu_buffer_rsrc_t w = make_rsrc(dstb + 2 * (int64_t)lb, lb);
 #pragma unroll
                     for (int q = 0; q < 27; ++q) {
-                        T v = k.scale_g * t[q] * inv_wgt3<T>(q);
+                        T v = encode3<S>(t[q], k.enc_g, q);
                         if (WALLS && wdir != 0 && EYd(q) == wdir) v += wcorr * T(EXd(q));
                         Buf<S>::template store<CP>(w, vo, q * pb, v, rs + weyl(3 * q + 2));
                     }
@@ -930,7 +982,7 @@ __global__ __launch_bounds__(WG3) void k_init3(const InitArgs3 a) {
         for (int q = 0; q < 27; ++q) {
             int pa, node;
             pull_slot3(x, y, z, q, nx, ny, nz, a.walls, pa, node);
-            const double v = ((s - qref) + t[q] * inv_wgt3<double>(q)) * scale;
+            const double v = ((s - qref) + t[q] * enc_wgt3<double>(nnz3(q))) * scale;
             encode_store<S, T>(pop, (int64_t)(lat * 27 + pa) * vol + node, v);
         }
     }
@@ -953,7 +1005,7 @@ __global__ __launch_bounds__(WG3) void k_init3(const InitArgs3 a) {
             int pa, node;
             pull_slot3(x, y, z, q, nx, ny, nz, a.walls, pa, node);
             encode_store<S, T>(pop, (int64_t)(54 + pa) * vol + node,
-                               t[q] * inv_wgt3<double>(q) * k.scale_g);
+                               t[q] * enc_wgt3<double>(nnz3(q)) * k.scale_g);
         }
     }
     if (a.flow == FLOW_PRESCRIBED && a.ushape) {
