@@ -447,46 +447,71 @@ __device__ __forceinline__ void flow_dev27(const T eta2[6], T dP, T rho, T ux, T
 }
 
 // Isotropic D3Q27 stencils at in-plane index idx of three LDS planes
-// (z - 1, z, z + 1; row pitch PX): gradient d_i = (1/cs2) sum_a w_a e_ai
-// F(x + e_a) and divergence (1/cs2) sum_a w_a e_a . V(x + e_a).
-// No FP contraction: a value computed at a node carries the same bits
-// whichever kernel instance (launch shape) computes it.
+// (z - 1, z, z + 1; row pitch PX): gradient d_i F = (1/cs2) sum_a w_a e_ai
+// F(x + e_a) and divergence (1/cs2) sum_a w_a e_a . V(x + e_a).  The weights
+// are products w(e_ax) w(e_ay) w(e_az) with w(0) = 2/3, w(+-1) = 1/6, so a
+// component is a central difference along its axis smoothed with (1, 4, 1)
+// along the other two: d_x F = (1/72) sum_jk (1,4,1)_j (1,4,1)_k
+// (F(+1, j, k) - F(-1, j, k)).  The same expressions serve every node, so a
+// value computed at a node carries the same bits whichever kernel instance
+// (launch shape) computes it.
+template <class T>
+__device__ __forceinline__ T smooth3(T a, T b, T c) {
+    return fma(T(4), b, a + c);
+}
+// F at the 26 neighbours: v[k][j][i] = F at offset (i - 1, j - 1, k - 1)
+template <class T, int PX>
+__device__ __forceinline__ void cube3(const T* Lm, const T* L0, const T* Lp, int idx, T v[3][3][3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T* L = k == 0 ? Lm : (k == 1 ? L0 : Lp);
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i != 1 || j != 1 || k != 1) v[k][j][i] = L[idx + (i - 1) + (j - 1) * PX];
+    }
+}
+// the three smoothed central-difference sums (72 times the gradient)
+template <class T>
+__device__ __forceinline__ void dsum3(const T v[3][3][3], T& sx, T& sy, T& sz) {
+    T a[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        a[k] = smooth3(v[k][0][2] - v[k][0][0], v[k][1][2] - v[k][1][0], v[k][2][2] - v[k][2][0]);
+    sx = smooth3(a[0], a[1], a[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        a[k] = smooth3(v[k][2][0] - v[k][0][0], v[k][2][1] - v[k][0][1], v[k][2][2] - v[k][0][2]);
+    sy = smooth3(a[0], a[1], a[2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        a[j] = smooth3(v[2][j][0] - v[0][j][0], v[2][j][1] - v[0][j][1], v[2][j][2] - v[0][j][2]);
+    sz = smooth3(a[0], a[1], a[2]);
+}
 template <class T, int PX>
 __device__ __forceinline__ void grad3p(const T* Lm, const T* L0, const T* Lp, int idx, T& gx,
                                        T& gy, T& gz) {
-#pragma clang fp contract(off)
-    T sx = T(0), sy = T(0), sz = T(0);
-#pragma unroll
-    for (int a = 1; a < 27; ++a) {
-        const int ex = EXd(a), ey = EYd(a), ez = EZd(a);
-        const T* L = ez < 0 ? Lm : (ez > 0 ? Lp : L0);
-        const T v = wgt3<T>(a) * L[idx + ex + ey * PX];
-        if (ex) sx += ex > 0 ? v : -v;
-        if (ey) sy += ey > 0 ? v : -v;
-        if (ez) sz += ez > 0 ? v : -v;
-    }
-    gx = T(3) * sx;
-    gy = T(3) * sy;
-    gz = T(3) * sz;
+    T v[3][3][3];
+    cube3<T, PX>(Lm, L0, Lp, idx, v);
+    T sx, sy, sz;
+    dsum3(v, sx, sy, sz);
+    gx = sx * T(1.0 / 72.0);
+    gy = sy * T(1.0 / 72.0);
+    gz = sz * T(1.0 / 72.0);
 }
 
 // components of V are NP apart in each plane
 template <class T, int PX, int NP>
 __device__ __forceinline__ T div3p(const T* Vm, const T* V0, const T* Vp, int idx) {
-#pragma clang fp contract(off)
-    T s = T(0);
-#pragma unroll
-    for (int a = 1; a < 27; ++a) {
-        const int ex = EXd(a), ey = EYd(a), ez = EZd(a);
-        const T* V = ez < 0 ? Vm : (ez > 0 ? Vp : V0);
-        const int j = idx + ex + ey * PX;
-        T d = T(0);
-        if (ex) d += ex > 0 ? V[j] : -V[j];
-        if (ey) d += ey > 0 ? V[NP + j] : -V[NP + j];
-        if (ez) d += ez > 0 ? V[2 * NP + j] : -V[2 * NP + j];
-        s += wgt3<T>(a) * d;
-    }
-    return T(3) * s;
+    T v[3][3][3], sx, sy, sz, unused0, unused1;
+    cube3<T, PX>(Vm, V0, Vp, idx, v);
+    dsum3(v, sx, unused0, unused1);
+    cube3<T, PX>(Vm + NP, V0 + NP, Vp + NP, idx, v);
+    dsum3(v, unused0, sy, unused1);
+    cube3<T, PX>(Vm + 2 * NP, V0 + 2 * NP, Vp + 2 * NP, idx, v);
+    dsum3(v, unused0, unused1, sz);
+    return ((sx + sy) + sz) * T(1.0 / 72.0);
 }
 
 // n = grad phi/(|grad phi| + eps)
