@@ -110,7 +110,9 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
 /* Initialise simulation `sim` from host fields (each [ny][nx], FP64).
  * phi and c are required.  ux, uy: velocity (NULL = 0); for
  * CMLB_FLOW_PRESCRIBED they are the spatial shape u_shape used every step.
- * p: pressure (NULL = rho(phi) cs^2).  Populations are set to the
+ * p: pressure (NULL = rho(phi) cs^2; with rho_a != rho_b that default
+ * jumps by cs^2 (rho_a - rho_b) across the interface, so a drop meant to
+ * start near rest takes a uniform p).  Populations are set to the
  * central-moment equilibria of App. C, Sec. 3 and App. D for these fields
  * (the paper initialises the fields only, Sec. 4).  Resets the step
  * counter of the context to 0.  Synchronous. */

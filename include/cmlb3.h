@@ -57,9 +57,11 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
 
 /* Initialise simulation `sim` from host fields ([nz][ny][nx] FP64; phi and c
  * required; u components NULL = 0, the prescribed velocity's spatial shape
- * for CMLB_FLOW_PRESCRIBED; p NULL = rho(phi) cs^2).  Populations are set
- * to the central-moment equilibria of these fields.  Resets the step
- * counter.  Synchronous. */
+ * for CMLB_FLOW_PRESCRIBED; p NULL = rho(phi) cs^2, which with rho_a !=
+ * rho_b jumps by cs^2 (rho_a - rho_b) across the interface: a drop meant to
+ * start near rest takes a uniform p).  Populations are set to the
+ * central-moment equilibria of these fields.  Resets the step counter.
+ * Synchronous. */
 int cmlb3_init_fields(cmlb3_ctx* ctx, int32_t sim, const double* phi, const double* c,
                       const double* ux, const double* uy, const double* uz, const double* p);
 

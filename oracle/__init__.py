@@ -18,7 +18,10 @@ import sys
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB names a build of the same sources with a planted mistake
+# (-DORACLE_PLANT=k); only the test of the pins themselves sets it.
+PLANTED_LIB = os.environ.get("ORACLE_LIB")
+LIB_PATH = PLANTED_LIB or os.path.join(HERE, "liboracle.so")
 SRC = os.path.join(HERE, "cmlb_oracle.c")
 SRC3 = os.path.join(HERE, "cmlb3_oracle.c")
 SOURCES = (SRC, SRC3, os.path.join(HERE, "cmlb_oracle.h"), os.path.join(HERE, "cmlb3_oracle.h"))
@@ -30,16 +33,18 @@ DIAG_NAMES = (
 )
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, plant: int = 0, out: str | None = None) -> str:
     """Compile the oracle with gcc (OpenMP over rows; results do not depend on
-    the thread count because no value is reduced across threads)."""
+    the thread count because no value is reduced across threads).  ``plant``
+    builds a copy with planted mistake ``plant`` into ``out`` instead."""
+    path = out or os.path.join(HERE, "liboracle.so")
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE",
-           "-Wall", SRC, SRC3, "-o", LIB_PATH + ".tmp", "-lm"]
+           "-Wall", f"-DORACLE_PLANT={int(plant)}", SRC, SRC3, "-o", path + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.check_call(cmd)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(path + ".tmp", path)
+    return path
 
 
 class OParams(ctypes.Structure):
@@ -62,8 +67,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or any(
-                os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in SOURCES):
+        if not PLANTED_LIB and (not os.path.exists(LIB_PATH) or any(
+                os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in SOURCES)):
             build()
         L = ctypes.CDLL(LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)

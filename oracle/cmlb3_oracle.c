@@ -55,6 +55,13 @@
 
 #include "cmlb3_oracle.h"
 
+/* Planted mistakes (see cmlb_oracle.c): built with -DORACLE_PLANT=k for the
+ * test suite's check of its pins; the default build computes the method. */
+#ifndef ORACLE_PLANT
+#define ORACLE_PLANT 0
+#endif
+#define PLANT(k) (ORACLE_PLANT == (k))
+
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -107,8 +114,9 @@ void o3_central_moments(const double q[27], const double u[3], double out[27]) {
 static void axis_inverse(double k0, double k1, double k2, double u, double out[3]) {
     const double r0 = k0, r1 = k1 + u * k0, r2 = k2 + 2.0 * u * k1 + u * u * k0;
     out[0] = r0 - r2;
-    out[1] = 0.5 * (r2 + r1);
-    out[2] = 0.5 * (r2 - r1);
+    /* plant 22: the two moving populations swapped */
+    out[PLANT(22) ? 2 : 1] = 0.5 * (r2 + r1);
+    out[PLANT(22) ? 1 : 2] = 0.5 * (r2 - r1);
 }
 
 void o3_populations_from_central(const double kappa[27], const double u[3], double q[27]) {
@@ -233,7 +241,8 @@ void o3_collide_flow(const double g[27], const double u[3], double P, double rho
             if (a == b)
                 src[m] = 2.0 * CS2 * fp[a] * u[a] + (u[a] * u[a] + CS2) * gam;
             else
-                src[m] = CS2 * (fp[a] * u[b] + fp[b] * u[a]) + u[a] * u[b] * gam;
+                /* plant 25: the u u gamma term of the off-diagonal source dropped */
+                src[m] = CS2 * (fp[a] * u[b] + fp[b] * u[a]) + (PLANT(25) ? 0.0 : u[a] * u[b] * gam);
         }
         /* rate 1 unless second order (below) */
         th[m] = eta[m] + (eq[m] - eta[m]) + 0.5 * src[m];
@@ -252,7 +261,9 @@ void o3_collide_flow(const double g[27], const double u[3], double P, double rho
         Te += eq[dg[r]];
         Ts += src[dg[r]];
     }
-    const double Tt = T + omega_zeta * (Te - T) + (1.0 - 0.5 * omega_zeta) * Ts;
+    /* plant 23: the trace relaxed at the shear rate */
+    const double om_tr = PLANT(23) ? omega_nu : omega_zeta;
+    const double Tt = T + om_tr * (Te - T) + (1.0 - 0.5 * om_tr) * Ts;
     for (int r = 0; r < 3; ++r) {
         const int m = dg[r];
         const double d = eta[m] - T / 3.0, de = eq[m] - Te / 3.0, ds = src[m] - Ts / 3.0;
@@ -304,7 +315,8 @@ static void grad3(const o3_params* p, const double* F, const double w[27], int x
         s[1] += w[a] * ey_of(a) * v;
         s[2] += w[a] * ez_of(a) * v;
     }
-    for (int i = 0; i < 3; ++i) g[i] = s[i] / CS2;
+    /* plant 21: the factor 1/cs2 of the isotropic gradient dropped */
+    for (int i = 0; i < 3; ++i) g[i] = PLANT(21) ? s[i] : s[i] / CS2;
 }
 
 /* Unit normal arrays with one ghost plane below and above in y (rows -1 and
@@ -372,6 +384,9 @@ static double curvature3(const o3_params* p, const fields3_t* F, const double w[
         const int xs = wrap(x + ex_of(a), p->nx), ys = y + ey_of(a), zs = wrap(z + ez_of(a), p->nz);
         const int yy = p->walls ? ys : wrap(ys, p->ny);
         const size_t i = NIDX(p, xs, yy, zs);
+        /* plant 26: the corner directions left out of the curvature */
+        const int corner = ex_of(a) && ey_of(a) && ez_of(a);
+        if (PLANT(26) && corner) continue;
         s += w[a] * (ex_of(a) * F->nrm[0][i] + ey_of(a) * F->nrm[1][i] + ez_of(a) * F->nrm[2][i]);
     }
     return s / CS2;
@@ -553,7 +568,9 @@ int o3_step(const o3_params* p, int64_t t, const double* ushape, const double* f
                                     tg);
                 }
                 for (int a = 0; a < 27; ++a) {
-                    int xd = wrap(x + ex_of(a), p->nx), yd = y + ey_of(a), zd = wrap(z + ez_of(a), p->nz);
+                    /* plant 24: streamed against the direction along z */
+                    int xd = wrap(x + ex_of(a), p->nx), yd = y + ey_of(a),
+                        zd = wrap(z + (PLANT(24) ? -ez_of(a) : ez_of(a)), p->nz);
                     int ad = a;
                     double corr = 0.0;
                     if (p->walls && (yd < 0 || yd >= p->ny)) {

@@ -72,6 +72,15 @@
 
 #include "cmlb_oracle.h"
 
+/* Planted mistakes.  The test suite checks that its pins catch plausible
+ * mistakes by building this file with -DORACLE_PLANT=k, which swaps in one
+ * wrong expression; the default build (k = 0) computes the method.  Each
+ * PLANT(k) site names its mistake. */
+#ifndef ORACLE_PLANT
+#define ORACLE_PLANT 0
+#endif
+#define PLANT(k) (ORACLE_PLANT == (k))
+
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -115,7 +124,9 @@ void o_central_moments(const double q[9], double ux, double uy, double out[9]) {
     for (int k = 0; k < 9; ++k) {
         double s = 0.0;
         for (int a = 0; a < 9; ++a)
-            s += q[a] * ipow(EX[a] - ux, MM[k]) * ipow(EY[a] - uy, NN[k]);
+            /* plant 11: moments about -u */
+            s += q[a] * ipow(EX[a] + (PLANT(11) ? ux : -ux), MM[k]) *
+                 ipow(EY[a] + (PLANT(11) ? uy : -uy), NN[k]);
         out[k] = s;
     }
 }
@@ -179,10 +190,14 @@ void o_directions(int ex[9], int ey[9]) {
 /* ---------------------------------------------------------------------- */
 
 double o_langmuir(double sigma0, double beta, double c_max, double c) {
-    return sigma0 * (1.0 + beta * log(1.0 - c / c_max));
+    /* plant 13: decimal instead of natural logarithm */
+    return sigma0 * (1.0 + beta * (PLANT(13) ? log10(1.0 - c / c_max) : log(1.0 - c / c_max)));
 }
 
-double o_omega_from_transport(double coeff) { return 1.0 / (coeff / CS2 + 0.5); }
+/* plant 5: the transport coefficient taken as tau - 1/2 without 1/cs2 */
+double o_omega_from_transport(double coeff) {
+    return 1.0 / ((PLANT(5) ? coeff : coeff / CS2) + 0.5);
+}
 
 static double lin_phi(const o_params* p, double phi, double va, double vb) {
     return vb + (phi - p->phi_b) / (p->phi_a - p->phi_b) * (va - vb);
@@ -224,8 +239,9 @@ int o_collide_flow(const double g[9], double ux, double uy, double P, double rho
     const double psi = P - rho * CS2;
     const double ux2 = ux * ux, uy2 = uy * uy;
     eq[0] = P;
-    eq[1] = -psi * ux;
-    eq[2] = -psi * uy;
+    /* plant 2: the first-order equilibria with the sign as printed */
+    eq[1] = (PLANT(2) ? psi : -psi) * ux;
+    eq[2] = (PLANT(2) ? psi : -psi) * uy;
     eq[3] = CS2 * P + psi * ux2;
     eq[4] = CS2 * P + psi * uy2;
     eq[5] = psi * ux * uy;
@@ -236,8 +252,9 @@ int o_collide_flow(const double g[9], double ux, double uy, double P, double rho
     src[0] = gam;
     src[1] = CS2 * ftx - ux * gam;
     src[2] = CS2 * fty - uy * gam;
-    src[3] = 2.0 * CS2 * fpx * ux + (ux2 + CS2) * gam;
-    src[4] = 2.0 * CS2 * fpy * uy + (uy2 + CS2) * gam;
+    /* plant 3: factor 2 of the diagonal second-order sources dropped */
+    src[3] = (PLANT(3) ? 1.0 : 2.0) * CS2 * fpx * ux + (ux2 + CS2) * gam;
+    src[4] = (PLANT(3) ? 1.0 : 2.0) * CS2 * fpy * uy + (uy2 + CS2) * gam;
     src[5] = CS2 * (fpx * uy + fpy * ux) + ux * uy * gam;
     src[6] = 0.0;
     src[7] = 0.0;
@@ -263,7 +280,8 @@ int o_collide_flow(const double g[9], double ux, double uy, double P, double rho
     }
     double lam[9];
     for (int i = 0; i < 9; ++i) lam[i] = 1.0;
-    lam[3] = omega_zeta;
+    /* plant 17: the sum of the diagonal moments relaxed at the shear rate */
+    lam[3] = PLANT(17) ? omega_nu : omega_zeta;
     lam[4] = omega_nu;
     lam[5] = omega_nu;
     double th[9];
@@ -271,8 +289,9 @@ int o_collide_flow(const double g[9], double ux, double uy, double P, double rho
     /* B^-1: bare second-order moments from their sum and difference. */
     double tb[9];
     for (int i = 0; i < 9; ++i) tb[i] = th[i];
-    tb[3] = 0.5 * (th[3] + th[4]);
-    tb[4] = 0.5 * (th[3] - th[4]);
+    /* plant 4: B^-1 without its factor 1/2 */
+    tb[3] = (PLANT(4) ? 1.0 : 0.5) * (th[3] + th[4]);
+    tb[4] = (PLANT(4) ? 1.0 : 0.5) * (th[3] - th[4]);
     return o_populations_from_central(tb, ux, uy, gt);
 }
 
@@ -315,8 +334,9 @@ static void grad_field(const o_params* p, const double* F, const double w[9], in
         sx += w[a] * EX[a] * v;
         sy += w[a] * EY[a] * v;
     }
-    *gx = sx / CS2;
-    *gy = sy / CS2;
+    /* plant 6: the factor 1/cs2 of the isotropic gradient dropped */
+    *gx = PLANT(6) ? sx : sx / CS2;
+    *gy = PLANT(6) ? sy : sy / CS2;
 }
 
 /* Per-node macroscopic and geometric state at time n. */
@@ -384,7 +404,8 @@ static void compute_fields(const o_params* p, const double w[9], const double* f
             F->c[IDX(p, x, y)] = sh;
             F->phat[IDX(p, x, y)] = sg;
             double rho = lin_phi(p, sf, p->rho_a, p->rho_b);
-            F->psih[IDX(p, x, y)] = sg - rho * CS2;
+            /* plant 16: F_p from P^ instead of psi^ = P^ - rho cs2 */
+            F->psih[IDX(p, x, y)] = PLANT(16) ? sg : sg - rho * CS2;
         }
 #pragma omp parallel for schedule(static)
     for (int y = -1; y <= ny; ++y)
@@ -406,7 +427,8 @@ static double curvature(const o_params* p, const fields_t* F, const double w[9],
         int ys = y + EY[a];
         s += w[a] * (EX[a] * NRM(F, p, xs, ys) + EY[a] * NRMY(F, p, xs, ys));
     }
-    return s / CS2;
+    /* plant 7: curvature with the opposite sign */
+    return (PLANT(7) ? -s : s) / CS2;
 }
 
 /* Steps 2-4 at one node. */
@@ -427,8 +449,9 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
     s->ny = NRMY(F, p, x, y);
     const double dphi = p->phi_a - p->phi_b;
     const double phim = 0.5 * (p->phi_a + p->phi_b);
-    s->theta = (4.0 / p->W) * (p->phi_a - s->phi) * (s->phi - p->phi_b) / dphi;
-    s->theta_c = (8.0 * s->c / p->W) * (phim - s->phi) / dphi;
+    /* plant 10: sharpening flux dropped; plant 9: confining coefficient 4/W */
+    s->theta = PLANT(10) ? 0.0 : (4.0 / p->W) * (p->phi_a - s->phi) * (s->phi - p->phi_b) / dphi;
+    s->theta_c = ((PLANT(9) ? 4.0 : 8.0) * s->c / p->W) * (phim - s->phi) / dphi;
 
     if (p->flow == O_FLOW_COUPLED) {
         /* curvature: divergence of the unit normal, same stencil */
@@ -442,7 +465,9 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
         double dsig = -p->sigma0 * p->beta / (p->c_max - s->c);
         double gsx = dsig * s->gcx, gsy = dsig * s->gcy;
         double nd = s->nx * gsx + s->ny * gsy;
-        double tsx = gsx - s->nx * nd, tsy = gsy - s->ny * nd;
+        /* plant 15: normal part added instead of removed */
+        double tsx = PLANT(15) ? gsx + s->nx * nd : gsx - s->nx * nd;
+        double tsy = PLANT(15) ? gsy + s->ny * nd : gsy - s->ny * nd;
         double weight, ks;
         const double phio = 0.5 * dphi;
         if (p->force_abs_grad) {
@@ -450,7 +475,8 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
             ks = 1.0 / dphi;
         } else {
             weight = s->gmag * s->gmag;
-            ks = 3.0 * p->W / (8.0 * phio * phio);
+            /* plant 1: F_s without the normalisation k_s */
+            ks = PLANT(1) ? 1.0 : 3.0 * p->W / (8.0 * phio * phio);
         }
         s->fsx = ks * weight * (-s->sigma * s->curv * s->nx + tsx);
         s->fsy = ks * weight * (-s->sigma * s->curv * s->ny + tsy);
@@ -464,8 +490,9 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
         }
         s->jx = jx;
         s->jy = jy;
-        s->ux = (jx + 0.5 * CS2 * s->ftx) / (CS2 * s->rho);
-        s->uy = (jy + 0.5 * CS2 * s->fty) / (CS2 * s->rho);
+        /* plant 14: velocity without the half-force correction */
+        s->ux = (jx + (PLANT(14) ? 0.0 : 0.5) * CS2 * s->ftx) / (CS2 * s->rho);
+        s->uy = (jy + (PLANT(14) ? 0.0 : 0.5) * CS2 * s->fty) / (CS2 * s->rho);
         double fpx = -s->gpsix, fpy = -s->gpsiy;
         s->P = s->P_hat + 0.5 * (fpx * s->ux + fpy * s->uy);
     } else if (p->flow == O_FLOW_PRESCRIBED) {
@@ -611,8 +638,9 @@ int o_step(const o_params* p, int64_t t, const double* ux_shape, const double* u
             if (bad) fault |= 4;
             /* streaming: q(x + e, t + 1) = q~(x, t) */
             for (int a = 0; a < 9; ++a) {
-                int xd = wrap_x(p, x + EX[a]);
-                int yd = y + EY[a];
+                /* plant 12: streamed against the direction */
+                int xd = wrap_x(p, x + (PLANT(12) ? -EX[a] : EX[a]));
+                int yd = y + (PLANT(12) ? -EY[a] : EY[a]);
                 int ad = a;
                 double corr = 0.0;
                 if (p->walls && (yd < 0 || yd >= ny)) {
@@ -620,7 +648,8 @@ int o_step(const o_params* p, int64_t t, const double* ux_shape, const double* u
                     ad = opposite(a);
                     xd = x;
                     double uw = (yd < 0) ? -p->u_wall : p->u_wall;
-                    corr = 2.0 * w[ad] * s.rho * (EX[ad] * uw);
+                    /* plant 8: correction with the incoming direction */
+                    corr = 2.0 * w[ad] * s.rho * (EX[PLANT(8) ? a : ad] * uw);
                     yd = y;
                 } else {
                     yd = wrap_y(p, yd);

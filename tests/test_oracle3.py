@@ -258,3 +258,35 @@ def test_scalar_step_fourier_mode_exact3(oracle_mod, kv):
     assert np.abs(s.h - expect).max() <= 1e-13 * np.abs(expect).max()
     kk = sum(kc * kc for kc in k)
     assert abs(abs(lam[i]) / math.exp(-D * kk) - 1) < 0.05 * kk
+
+
+@pytest.mark.parametrize("omega_zeta", [0.8, 1.5])
+def test_sound_wave_damping_3d(oracle_mod, omega_zeta):
+    """A small standing pressure wave P = P0 + A cos(kx) decays at
+    (k^2/2)(4 nu/3 + nu_b), nu_b = (2/3) cs2 (1/omega_zeta - 1/2): linear
+    isothermal acoustics in 3D with the trace of the second-order moments
+    relaxed at omega_zeta and its deviatoric part at the shear rate.  The
+    rate comes from the decay of the wave's energy,
+    (P' amplitude)^2/(rho cs2) + rho (u amplitude)^2."""
+    n, nu, A = 48, 0.1, 1e-6
+    p = oracle_mod.make_params3(nx=n, ny=4, nz=4, walls=0, flow="coupled", W=4.0, phi_a=1.0,
+                                phi_b=0.0, M_phi=0.1, D_s=0.1, rho_a=1.0, rho_b=1.0, nu_a=nu,
+                                nu_b=nu, omega_zeta=omega_zeta, sigma0=0.0, beta=0.0, c_max=1.0)
+    x = np.arange(n)[None, None, :] * np.ones((4, 4, n))
+    k = 2 * np.pi / n
+    P0 = 1.0 / 3.0
+    o = oracle_mod.OracleSim3(p, np.ones((4, 4, n)), np.zeros((4, 4, n)), None, None, None,
+                              P0 + A * np.cos(k * x))
+    t, q = [], []
+    for s in range(0, 300, 4):
+        f = o.fields()
+        a = 2 * ((f["P"] - P0) * np.cos(k * x)).mean()
+        b = 2 * (f["ux"] * np.sin(k * x)).mean()
+        t.append(s)
+        q.append(3.0 * a * a + b * b)
+        o.run(4)
+    t, q = np.array(t), np.array(q)
+    keep = t >= 40
+    gamma = -np.polyfit(t[keep], np.log(q[keep]), 1)[0] / 2
+    expect = 4.0 * nu / 3.0 + (2.0 / 3.0) * (1.0 / 3.0) * (1.0 / omega_zeta - 0.5)
+    assert abs(gamma / (k * k / 2) / expect - 1) < 0.015, (gamma / (k * k / 2), expect)
