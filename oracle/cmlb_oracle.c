@@ -441,7 +441,8 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
     s->c = F->c[i];
     s->P_hat = F->phat[i];
     s->rho = lin_phi(p, s->phi, p->rho_a, p->rho_b);
-    s->nu = lin_phi(p, s->phi, p->nu_a, p->nu_b);
+    /* plant 18: the two viscosities interchanged */
+    s->nu = PLANT(18) ? lin_phi(p, s->phi, p->nu_b, p->nu_a) : lin_phi(p, s->phi, p->nu_a, p->nu_b);
 
     grad_field(p, F->phi, w, x, y, &s->gphix, &s->gphiy);
     s->gmag = sqrt(s->gphix * s->gphix + s->gphiy * s->gphiy);

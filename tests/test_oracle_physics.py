@@ -21,7 +21,12 @@ a dropped term, a wrong sign or a transposed operand fails one of them:
 * the Marangoni part of F_s lying in the interface (the surface gradient of
   Eq. Fs),
 * a layer of twice the density carried by a uniform flow: velocity and
-  pressure stay uniform (the F_p = -grad(P - rho cs2) coupling of App. D).
+  pressure stay uniform (the F_p = -grad(P - rho cs2) coupling of App. D),
+* two-layer Couette flow with a viscosity and density ratio: the shear
+  stress is continuous, so the bulk slopes stand in the inverse ratio of the
+  dynamic viscosities, and the stress is 2U over the sum of 1/mu(phi) across
+  the channel (rho and nu linear in phi, App. D),
+* Laplace's law unchanged by a density ratio.
 """
 import math
 
@@ -159,15 +164,18 @@ def test_couette_between_moving_walls(oracle_mod):
     assert np.abs(s.fields()["ux"] - ux).max() > 0.1 * U0
 
 
-def test_laplace_law(oracle_mod):
+@pytest.mark.parametrize("rho_a", [1.0, 2.0])
+def test_laplace_law(oracle_mod, rho_a):
     """Clean static drop: time-averaged P_in - P_out = sigma0/R.  With W = 4
     the isotropic gradient under-resolves |grad phi|^2 by about 7%, so the
-    ratio sits near 0.93 (the unnormalised force of Eq. Fs would give 1/6)."""
+    ratio sits near 0.93 (the unnormalised force of Eq. Fs would give 1/6).
+    A drop twice as dense as its surroundings, started from a uniform P,
+    gives the same ratio (0.9395 against 0.9397)."""
     n, R, sig = 48, 12.0, 0.01
     p = W.params(nx=n, ny=n, flow="coupled", sigma0=sig, beta=0.0, M_phi=0.05,
-                 D_s=0.01, omega_zeta=0.8)
+                 D_s=0.01, omega_zeta=0.8, rho_a=rho_a, rho_b=1.0)
     phi, c = W.drop_fields(n, n, n / 2, n / 2, R, 4.0, None)
-    s = _sim(oracle_mod, p, dict(phi=phi, c=c))
+    s = _sim(oracle_mod, p, dict(phi=phi, c=c, P=np.full_like(phi, 1.0 / 3.0)))
     s.run(1500)
     vals = []
     for _ in range(50):
@@ -387,3 +395,33 @@ def test_translating_density_layer(oracle_mod):
     com = lambda ph: np.angle((ph[0] * np.exp(2j * np.pi * np.arange(n) / n)).sum()) * n / (2 * np.pi)
     shift = (com(f["phi"]) - com(phi)) % n
     assert abs(shift - U * 300) < 0.1, shift
+
+
+def test_layered_couette_viscosity_ratio(oracle_mod):
+    """Two layers between the moving walls: fluid a (rho 2, nu 0.1) below a
+    flat interface at mid-height, fluid b (rho 1, nu 0.05) above.  In the
+    steady state the shear stress is the same at every height, so the bulk
+    slopes stand in the ratio mu_b/mu_a = 1/4 (mu = rho nu), and the stress is
+    2U / sum_j 1/mu(phi_j) over the rows between the wall planes, with rho
+    and nu linear in phi."""
+    nx, ny, U = 4, 32, 1e-3
+    ra, rb, na, nb = 2.0, 1.0, 0.1, 0.05
+    p = W.params(nx=nx, ny=ny, flow="coupled", bc_y="walls", u_wall=U, sigma0=0.0, beta=0.0,
+                 M_phi=0.02, D_s=0.01, rho_a=ra, rho_b=rb, nu_a=na, nu_b=nb)
+    y = np.arange(ny)[:, None] + 0.5 + 0 * np.arange(nx)[None, :]
+    phi = 0.5 + 0.5 * np.tanh(2 * (ny / 2 - y) / 4.0)
+    z = np.zeros_like(phi)
+    s = _sim(oracle_mod, p, dict(phi=phi, c=z, P=np.full_like(phi, rb / 3.0)))
+    assert s.run(20000) == 0
+    f = s.fields()
+    u, ph = f["ux"][:, 0], f["phi"][:, 0]
+    assert np.abs(f["ux"] - u[:, None]).max() < 1e-15
+    yy = np.arange(ny) + 0.5
+    la = (yy > 2) & (yy < ny / 2 - 8)
+    lb = (yy > ny / 2 + 8) & (yy < ny - 2)
+    sa = np.polyfit(yy[la], u[la], 1)[0]
+    sb = np.polyfit(yy[lb], u[lb], 1)[0]
+    assert abs((sa / sb) / (rb * nb / (ra * na)) - 1) < 1e-3, sa / sb
+    mu = (rb + ph * (ra - rb)) * (nb + ph * (na - nb))
+    tau = 2 * U / np.sum(1.0 / mu)
+    assert abs(ra * na * sa / tau - 1) < 3e-3, (ra * na * sa, tau)
