@@ -13,6 +13,8 @@ beyond the oracle's reach).
 * Single vortex (512 x 512, R = 64, U0 = 0.02, T = 20000): after the full
   reversal period the drop returns; one step deep in the run against the
   oracle at full size.
+* Density and viscosity ratios: two-layer Couette flow (mu_a/mu_b = 4) with
+  a continuous shear stress.
 """
 import math
 
@@ -248,3 +250,37 @@ def test_advected_sphere_3d(gpu_lib):
     print(f"advected sphere: decay {decay:.4f} expected {expected:.4f}; phi rel L2 {err:.2e}")
     assert abs(decay / expected - 1) < 0.05
     assert err < 2e-2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-3), ("fp32", 2e-3)])
+def test_layered_couette_viscosity_ratio(gpu_lib, prec, tol):
+    """Two fluid layers between the moving walls on the GPU path: fluid a
+    (rho 2, nu 0.1) below a flat interface at mid-height, fluid b (rho 1,
+    nu 0.05) above, 64 x 128, walls at +-U.  In the steady state the shear
+    stress is the same at every height: the bulk slopes stand in the ratio
+    mu_b/mu_a = 1/4 (mu = rho nu), and the stress is 2U / sum_j 1/mu(phi_j)
+    with rho and nu linear in phi (App. D)."""
+    nx, ny, U = 64, 128, 1e-3
+    ra, rb, na, nb = 2.0, 1.0, 0.1, 0.05
+    p = W.params(nx=nx, ny=ny, flow="coupled", bc_y="walls", u_wall=U, sigma0=0.0, beta=0.0,
+                 M_phi=0.02, D_s=0.01, rho_a=ra, rho_b=rb, nu_a=na, nu_b=nb)
+    y = np.arange(ny)[:, None] + 0.5 + 0 * np.arange(nx)[None, :]
+    phi = 0.5 + 0.5 * np.tanh(2 * (ny / 2 - y) / 4.0)
+    z = np.zeros_like(phi)
+    ctx = gpu_ctx(p, dict(phi=phi, c=z, P=np.full_like(phi, rb / 3.0)), prec)
+    ctx.step(300000)  # >= 9 decay times H^2/(pi^2 nu) of the slowest mode
+    f = ctx.read_fields(0)
+    ctx.close()
+    u, ph = f["ux"].mean(axis=1), f["phi"].mean(axis=1)
+    assert np.abs(f["ux"] - u[:, None]).max() < 1e-9 * U
+    yy = np.arange(ny) + 0.5
+    la = (yy > 4) & (yy < ny / 2 - 12)
+    lb = (yy > ny / 2 + 12) & (yy < ny - 4)
+    sa = np.polyfit(yy[la], u[la], 1)[0]
+    sb = np.polyfit(yy[lb], u[lb], 1)[0]
+    mu = (rb + ph * (ra - rb)) * (nb + ph * (na - nb))
+    tau = 2 * U / np.sum(1.0 / mu)
+    print(f"{prec}: slope ratio {sa / sb:.6f} (1/4), stress {ra * na * sa:.6e} vs {tau:.6e}",
+          flush=True)
+    assert abs((sa / sb) / (rb * nb / (ra * na)) - 1) < tol
+    assert abs(ra * na * sa / tau - 1) < 3e-3
