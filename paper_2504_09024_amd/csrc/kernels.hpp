@@ -90,12 +90,16 @@ __device__ __forceinline__ void load9_dev(__amdgpu_buffer_rsrc_t r, int vo, int 
 }
 
 // ---------------------------------------------------------------------------
-// Pulled loads.  For a node whose nine sources x - e_a all lie inside the
+// Pulled loads.  For a node whose nine sources x - e_a lie in rows of the
 // grid, the source shift goes into the scalar offset: so[a] = a*plane -
 // (e_ax + e_ay nx), in bytes (non-negative for a >= 1 because a plane holds
-// at least four rows), and the node offset is shared by all nine loads.
-// Near the domain edge the sources wrap (periodic) or, behind a wall, come
-// from the node's own opposite slot.
+// at least four rows), and the node offset is shared by all nine loads.  The
+// periodic wrap in x stays on this path: a node in column 0 pulls the
+// directions with e_ax = +1 from column nx - 1 (node offset + nx), a node in
+// column nx - 1 those with e_ax = -1 from column 0 (- nx); xp and xm carry
+// these per-lane corrections.  Near a wall, or on grids narrower than a
+// tile plus its halo, the sources wrap or come from the node's own opposite
+// slot on the general path.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void pull_offsets(int pb, int nx, int sb, int so[9]) {
 #pragma unroll
@@ -103,9 +107,18 @@ __device__ __forceinline__ void pull_offsets(int pb, int nx, int sb, int so[9]) 
 }
 
 template <class S, class T>
-__device__ __forceinline__ void pull9_inner(__amdgpu_buffer_rsrc_t r, int vo, const int so[9], T v[9]) {
+__device__ __forceinline__ void pull9_inner(__amdgpu_buffer_rsrc_t r, int vo, int xp, int xm,
+                                            const int so[9], T v[9]) {
 #pragma unroll
-    for (int a = 0; a < 9; ++a) v[a] = T(Buf<S>::load(r, vo, so[a]));
+    for (int a = 0; a < 9; ++a)
+        v[a] = T(Buf<S>::load(r, EXa(a) > 0 ? xp : (EXa(a) < 0 ? xm : vo), so[a]));
+}
+// node offset of column x in row y and its two wrap-corrected forms
+template <int SB>
+__device__ __forceinline__ void wrap_offsets(int x, int y, int nx, int& vo, int& xp, int& xm) {
+    vo = (y * nx + x) * SB;
+    xp = x == 0 ? vo + nx * SB : vo;
+    xm = x == nx - 1 ? vo - nx * SB : vo;
 }
 
 template <class S, class T, bool WALLS>
@@ -237,7 +250,10 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const int64_t step = *a.step_in;
     // tile, its radius-2 halo and their pull sources inside the grid: no
     // wrapping, no walls
-    const bool inner = x0 >= 3 && x0 + TW + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
+    // tile, its radius-2 halo and their pull sources clear of the walls (or
+    // of the y wrap), on a grid at least a tile and its halo wide: x wraps
+    // per lane on the fast path
+    const bool inner = y0 >= 3 && y0 + TY + 3 <= ny && nx >= TW + 3;
     int so[9];
     pull_offsets(pb, nx, SB, so);
 
@@ -246,7 +262,9 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const int wave = tid / TW;        // row block of this wavefront
     const int lane = tid & (TW - 1);  // column within the tile
     const int gx = x0 + lane;
-    const int lx = inner ? gx : wrap_coord(gx, nx);
+    // lanes past the right edge of a ragged tile load the wrapped column;
+    // they store nothing
+    const int lx = inner ? (gx < nx ? gx : gx - nx) : wrap_coord(gx, nx);
 
     // ---------------- phase 1: own nodes -----------------------------------
     T qf[NPT][9], qh[NPT][9], qg[CPL ? NPT : 1][9];
@@ -257,10 +275,11 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         const int iy = wave * NPT + j;
         const int gy = y0 + iy;
         if (inner) {
-            const int vo = (gy * nx + gx) * SB;
-            pull9_inner<S, T>(rF, vo, so, qf[j]);
-            pull9_inner<S, T>(rH, vo, so, qh[j]);
-            if constexpr (CPL) pull9_inner<S, T>(rG, vo, so, qg[j]);
+            int vo, xp, xm;
+            wrap_offsets<SB>(lx, gy, nx, vo, xp, xm);
+            pull9_inner<S, T>(rF, vo, xp, xm, so, qf[j]);
+            pull9_inner<S, T>(rH, vo, xp, xm, so, qh[j]);
+            if constexpr (CPL) pull9_inner<S, T>(rG, vo, xp, xm, so, qg[j]);
         } else {
             const int ly = WALLS ? mirror_coord(gy, ny) : wrap_coord(gy, ny);
             pull9_edge<S, T, WALLS>(rF, pb, lx, ly, nx, ny, qf[j]);
@@ -311,14 +330,16 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         const int qi = (ry - 1) * QW + rx - 1;
         T q[9];
         if (inner) {
-            const int vo = (hy * nx + hx) * SB;
-            pull9_inner<S, T>(rF, vo, so, q);
+            hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
+            int vo, xp, xm;
+            wrap_offsets<SB>(hx, hy, nx, vo, xp, xm);
+            pull9_inner<S, T>(rF, vo, xp, xm, so, q);
             phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
             if (r1) {
-                pull9_inner<S, T>(rH, vo, so, q);
+                pull9_inner<S, T>(rH, vo, xp, xm, so, q);
                 cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
                 if constexpr (CPL) {
-                    pull9_inner<S, T>(rG, vo, so, q);
+                    pull9_inner<S, T>(rG, vo, xp, xm, so, q);
                     to_dev<S, T>(q, k.inv_g);
                     pL[qi] = zeroth(q);
                 }
@@ -370,7 +391,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     for (int j = 0; j < NPT; ++j) {
         const int iy = wave * NPT + j;
         const int gy = y0 + iy;
-        const bool valid = inner || (gx < nx && gy < ny);
+        const bool valid = gx < nx && gy < ny;
         const int pidx = (iy + 2) * PW + lane + 2;
         const int qidx = (iy + 1) * QW + lane + 1;
         const T phi = phv[j], c = cv[j];

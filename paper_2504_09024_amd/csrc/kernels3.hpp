@@ -161,11 +161,16 @@ __device__ __forceinline__ void pull27(__amdgpu_buffer_rsrc_t r, int pb, int x, 
     constexpr int SB = sizeof(S);
     const int plane = nx * ny;
     if (inner) {
+        // rows y - 1 .. y + 1 and planes z - 1 .. z + 1 in the grid; the
+        // periodic wrap in x per lane: column 0 pulls e_x = +1 from column
+        // nx - 1, column nx - 1 pulls e_x = -1 from column 0
         const int vo = ((z * ny + y) * nx + x) * SB;
+        const int xp = x == 0 ? vo + nx * SB : vo;
+        const int xm = x == nx - 1 ? vo - nx * SB : vo;
 #pragma unroll
         for (int a = 0; a < 27; ++a) {
             const int so = a * pb - (EXd(a) + EYd(a) * nx + EZd(a) * plane) * SB;
-            v[a] = Buf<S>::raw(r, vo, so);
+            v[a] = Buf<S>::raw(r, EXd(a) > 0 ? xp : (EXd(a) < 0 ? xm : vo), so);
         }
         return;
     }
@@ -233,7 +238,9 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
     const int pb = vol * SB;
     const int lb = 27 * pb;
     const char* srcb = static_cast<const char*>(a.src) + sd->off * SB;
-    const bool inner = x >= 1 && x + 1 < nx && y >= 1 && y + 1 < ny && z >= 1 && z + 1 < nz;
+    // a wave holds one (y, z) row: the general path only for the rows next
+    // to the y and z ends of the grid
+    const bool inner = y >= 1 && y + 1 < ny && z >= 1 && z + 1 < nz;
     T* mom = static_cast<T*>(a.mom) + sd->moff + ((z * ny + y) * nx + x);
     // all pulls before the first store: a load issued after a store would
     // wait for that store as well.  Binary16 values are widened only after
