@@ -372,8 +372,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "multi-GPU sharding is a design note, not implemented", file=sys.stderr)
+        print(f"bench.py: the library steps its simulations on one GPU only (got --gpus "
+              f"{args.gpus}); sharding over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
