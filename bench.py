@@ -406,6 +406,18 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             out[f"{mib}MiB"] = round(2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
+            # the library's own copy kernel, default and non-temporal loads
+            # and stores
+            for nt in (False, True):
+                for _ in range(3):
+                    cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, nt, stream)
+                e0.record()
+                for _ in range(reps):
+                    cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, nt, stream)
+                e1.record()
+                torch.cuda.synchronize()
+                key = f"{mib}MiB_lib_{'nt' if nt else 'default'}"
+                out[key] = round(2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
             del a, b
         print(json.dumps({"copy_GBps_read_plus_write": out}), flush=True)
         return

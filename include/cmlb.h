@@ -205,6 +205,16 @@ int cmlb_autotune(cmlb_ctx* ctx, int32_t steps, int32_t* width, int32_t* rows, i
  * for plain row-major order (default).  Results do not depend on it. */
 int cmlb_set_tile_order(cmlb_ctx* ctx, int32_t group);
 
+/* Measurement aid, not part of the method: copy `bytes` of device memory
+ * from src to dst on hip_stream (NULL = the default stream), asynchronously,
+ * with 16-byte vector loads and stores, four per thread.  nontemporal = 1
+ * marks loads and stores non-temporal (streamed past the caches), 0 uses
+ * the default cache policy.  The plain-copy bandwidth it reaches is the
+ * practical ceiling the step's HBM fraction is read against.  Both pointers
+ * must be 16-byte aligned and bytes a multiple of 16 (CMLB_EINVAL
+ * otherwise); the caller owns both buffers, which must not overlap. */
+int cmlb_copy(const void* src, void* dst, int64_t bytes, int32_t nontemporal, void* hip_stream);
+
 int64_t cmlb_step_count(const cmlb_ctx* ctx);
 int32_t cmlb_num_sims(const cmlb_ctx* ctx);
 /* Message of the last error on this context (owned by the context). */

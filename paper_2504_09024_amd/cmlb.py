@@ -44,7 +44,7 @@ EXPORTS = (
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
     "cmlb_set_use_graph",
     "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy", "cmlb_autotune",
-    "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
+    "cmlb_copy", "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
 )
 
 EXPORTS3 = (
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.cmlb_set_store_policy.argtypes = [vp, ctypes.c_int32]
     ip = ctypes.POINTER(ctypes.c_int32)
     L.cmlb_autotune.argtypes = [vp, ctypes.c_int32, ip, ip, ip]
+    L.cmlb_copy.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
     L.cmlb_step_count.argtypes = [vp]
     L.cmlb_step_count.restype = ctypes.c_int64
     L.cmlb_num_sims.argtypes = [vp]
@@ -147,6 +148,18 @@ def load(path: str = LIB_PATH):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def device_copy(src_ptr: int, dst_ptr: int, nbytes: int, nontemporal: bool = False,
+                stream=None) -> None:
+    """cmlb_copy: asynchronous device-to-device copy on `stream` (a HIP
+    stream handle; None = the default stream).  A measurement aid for the
+    plain-copy bandwidth ceiling, not part of the method."""
+    L = load()
+    rc = L.cmlb_copy(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes),
+                     1 if nontemporal else 0, ctypes.c_void_p(stream) if stream else None)
+    if rc != 0:
+        raise CmlbError(rc, "cmlb_copy")
 
 
 def _dptr(a):

@@ -16,6 +16,31 @@
 
 using namespace cmlb;
 
+namespace cmlb {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Plain device copy (cmlb_copy): four 16-byte loads per thread, then four
+// stores; NT marks both non-temporal.
+template <bool NT>
+__global__ __launch_bounds__(256) void k_copy(const f32x4* __restrict__ a, f32x4* __restrict__ b,
+                                              int64_t n4) {
+    const int64_t base = (int64_t)blockIdx.x * (4 * 256) + threadIdx.x;
+    f32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n4) v[u] = NT ? __builtin_nontemporal_load(&a[i]) : a[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n4) {
+            if (NT) __builtin_nontemporal_store(v[u], &b[i]);
+            else b[i] = v[u];
+        }
+    }
+}
+}  // namespace cmlb
+
 namespace {
 
 constexpr int GRAPH_PAIRS = 8;  // a graph holds 2 * GRAPH_PAIRS steps
@@ -909,6 +934,24 @@ int cmlb_set_tile_order(cmlb_ctx* c, int32_t group) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->tile_group = group;
     return build_tiles(c);
+}
+
+int cmlb_copy(const void* src, void* dst, int64_t bytes, int32_t nontemporal, void* hip_stream) {
+    if (!src || !dst || bytes < 0 || (bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15) ||
+        (reinterpret_cast<uintptr_t>(dst) & 15) || (nontemporal != 0 && nontemporal != 1))
+        return CMLB_EINVAL;
+    const int64_t n4 = bytes / 16;
+    if (n4 == 0) return CMLB_OK;
+    const int64_t blocks = (n4 + 4 * 256 - 1) / (4 * 256);
+    if (blocks > 0x7fffffff) return CMLB_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const auto* a = static_cast<const cmlb::f32x4*>(src);
+    auto* b = static_cast<cmlb::f32x4*>(dst);
+    if (nontemporal)
+        hipLaunchKernelGGL(cmlb::k_copy<true>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n4);
+    else
+        hipLaunchKernelGGL(cmlb::k_copy<false>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n4);
+    return hipGetLastError() == hipSuccess ? CMLB_OK : CMLB_EDEVICE;
 }
 
 int64_t cmlb_step_count(const cmlb_ctx* c) { return c ? c->step : -1; }

@@ -143,3 +143,18 @@ def test_validation_before_device(lib):
     assert lib.cmlb_step_count(None) == -1
     assert lib.cmlb_last_error(None) == b"null context"
     lib.cmlb_destroy(None)
+
+
+def test_copy_validation_before_device(lib):
+    """cmlb_copy rejects null or misaligned pointers, sizes that are not a
+    multiple of 16 and an unknown cache policy before any device call; an
+    empty copy launches nothing."""
+    from paper_2504_09024_amd import cmlb
+    vp = ctypes.c_void_p
+    assert lib.cmlb_copy(None, vp(256), 16, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy(vp(257), vp(512), 16, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy(vp(256), vp(520), 16, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy(vp(256), vp(512), 24, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy(vp(256), vp(512), -16, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy(vp(256), vp(512), 16, 2, None) == cmlb.EINVAL
+    assert lib.cmlb_copy(vp(256), vp(512), 0, 1, None) == cmlb.OK

@@ -345,3 +345,20 @@ def test_mode_decay_on_gpu(gpu_lib):
     measured = -math.log(a1 / a0)
     expected = D * steps / R ** 2
     assert abs(measured / expected - 1) < 0.02, (measured, expected)
+
+
+@pytest.mark.parametrize("nontemporal", [False, True])
+def test_device_copy(gpu_lib, nontemporal):
+    """cmlb_copy (the plain-copy measurement aid) copies every byte, across
+    several blocks and a ragged tail, and nothing beyond."""
+    import torch
+    from paper_2504_09024_amd import cmlb
+    n = 3 * 1024 * 1024 + 12  # float32 values: 16-byte multiple, ragged tail
+    a = torch.arange(n, dtype=torch.float32, device="cuda")
+    b = torch.full((n + 64,), -1.0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, nontemporal,
+                     torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(b[:n], a)
+    assert bool((b[n:] == -1.0).all())
