@@ -11,8 +11,10 @@ over every node of every simulation; populations stay resident in HBM.
 
 Prints one JSON line: coupled MLUPS, the step kernel's roofline fraction
 (algorithmic bytes over HIP-event-timed launches on the kernel's stream),
-the other storage forms (FP64, FP16) of the batch and of the single
-1024x512 drop, and the CPU oracle timed on a bounded sample.
+the plain-copy ceiling measured in the same run (the library's copy with
+non-temporal loads and stores, 2 GiB buffers) and the step's fraction of it,
+the other storage forms (FP64, FP16) of the batch, of the single 1024x512
+drop and of the 3D drop, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
                        [--workload batched|c3]
@@ -266,6 +268,26 @@ WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2", "c5", "calib")
 FORM_WORKLOADS = ("batched", "c3", "c5")
 
 
+def copy_ceiling(torch, cmlb, stream, mib=2048, reps=20):
+    """Read + write GB/s of the library's plain copy (non-temporal loads and
+    stores) with two buffers of `mib` MiB: the practical HBM ceiling on the
+    device the benchmark runs on."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, True, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, True, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return gbps
+
+
 def workload(W, name):
     if name == "batched":
         sims = W.batched_shear_drops(64)
@@ -461,6 +483,12 @@ def main():
     log(f"[bench] {mlups:.0f} MLUPS, {ms_per_step * 1e3:.2f} us/step, {achieved:.0f} GB/s "
         f"({achieved / HBM_PEAK_GBS:.3f} of peak; wall {wall_s:.3f} s)")
 
+    # the plain-copy ceiling on this device, measured in the same run
+    copy_gbps = copy_ceiling(torch, cmlb, stream)
+    traffic = traffic_entry(args.workload, prec, 3 if dim3 else 2)
+    log(f"[bench] copy ceiling {copy_gbps:.0f} GB/s: step at {achieved / copy_gbps:.3f} of it "
+        f"in algorithmic bytes")
+
     forms = {f"{args.workload}_{prec}": {"MLUPS": round(mlups, 1),
                                          "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}}
     if not args.no_forms:
@@ -526,7 +554,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_entry(args.workload, prec, 3 if dim3 else 2),
+            "traffic": traffic,
+        },
+        "copy_ceiling": {
+            "value": round(copy_gbps, 1), "unit": "GB/s",
+            "kernel": "cmlb_copy, non-temporal loads and stores, two 2 GiB buffers",
+            "achieved_over_copy": round(achieved / copy_gbps, 4),
+            "traffic_over_copy": (round(traffic / (ms_per_step / 1e3) / 1e9 / copy_gbps, 4)
+                                  if traffic else None),
         },
         "cpu_baseline": cpu,
         "forms": forms,
