@@ -490,7 +490,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 const int own = gy * nx + gx;
                 const int vo = own * SB;
                 uint32_t rs = 0;
-                if constexpr (Store<S>::scaled) rs = fmix32(node_base + (uint32_t)own) ^ step_key;
+                if constexpr (Store<S>::scaled) rs = node_step_seed(node_base + (uint32_t)own, step_key);
                 // moving wall: the slots of directions pointing into the wall
                 // are pulled back by this node next step (half-way
                 // bounce-back); g carries the momentum correction

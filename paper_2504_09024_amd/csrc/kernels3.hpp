@@ -859,7 +859,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                 uint32_t rs = 0;
                 if constexpr (Store<S>::scaled) {
                     const uint32_t key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
-                    rs = fmix32(node_base + (uint32_t)own) ^ key;
+                    rs = cmlb::node_step_seed(node_base + (uint32_t)own, key);
                 }
                 T t[27];
                 // f: phase field

@@ -246,35 +246,45 @@ def test_sphere_surface_diffusion_l1(gpu_lib):
     c.close()
 
 
-def test_c5_5000_steps_fp32_tracks_fp64(gpu_lib):
+def test_c5_5000_steps_reduced_precision_tracks_fp64(gpu_lib):
     """The C5 configuration (256 x 128 x 128 coupled drop in shear, R = 32,
     Ca = 0.3, E = 0.2, c0 = 0.3, Re = 0.1) over its 5000 steps: no fault,
-    phi and c conserved, and the FP32 storage form stays near the FP64 one.
-    The bound is loose because the problem is: inside the drop phi sits at
-    1 + 2e-5, where the sharpening flux amplifies rounding-level structure by
-    ~0.7% per step (an FP64 run from phi perturbed by 1e-16 moves by 1.1e-6
-    relative after 2000 steps, the same 2D drop by 6e-9), so FP32's 1e-7
-    storage rounding grows to O(1e-4) in phi and O(1e-3) in the small bulk
-    surfactant values; the 2D C3 drop behaves alike (c: 2.9e-3 after
-    5000 steps).  A wrong term moves the fields by orders more."""
+    phi and c conserved, and the FP32 and FP16 storage forms stay near the
+    FP64 one.  The bound is loose because the problem is: inside the drop phi
+    sits at 1 + 2e-5, where the sharpening flux amplifies rounding-level
+    structure by ~0.7% per step (an FP64 run from phi perturbed by 1e-16
+    moves by 1.1e-6 relative after 2000 steps, the same 2D drop by 6e-9), so
+    FP32's 1e-7 storage rounding grows to O(1e-4) in phi and O(1e-3) in the
+    small bulk surfactant values; the 2D C3 drop behaves alike (c: 2.9e-3
+    after 5000 steps).  A wrong term moves the fields by orders more.
+    FP16 storage rounds stochastically; with random words hashed from the
+    (node, step) pair its inventories only random-walk (1e-5 after 5000
+    steps; 4.2M nodes put one standard deviation near 1e-4), where a seed
+    that XORs a node hash with a step hash drifted phi by 2.9e-3."""
     p, fl = W.shear_drop3()
     out = {}
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "fp16"):
         c = ctx3(p, fl, prec)
         s0 = c.inventory(0)
         c.step(5000)
         s1 = c.inventory(0)
         assert c.fault_flags(0) == 0
         drift = [abs(a - b) / abs(b) for a, b in zip(s1, s0)]
-        print(prec, "inventory drift phi, c:", [f"{d:.1e}" for d in drift])
-        assert drift[0] < (1e-13 if prec == "fp64" else 1e-5)
-        assert drift[1] < (1e-12 if prec == "fp64" else 1e-4)
+        print(prec, "inventory drift phi, c:", [f"{d:.1e}" for d in drift], flush=True)
+        bound = {"fp64": (1e-13, 1e-12), "fp32": (1e-5, 1e-4), "fp16": (5e-4, 5e-4)}[prec]
+        assert drift[0] < bound[0] and drift[1] < bound[1], (prec, drift)
         out[prec] = c.read_fields(0)
         c.close()
-    a, b = out["fp32"], out["fp64"]
-    err = {k: float(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])) for k in ("phi", "c")}
-    ua = np.stack([a["ux"], a["uy"], a["uz"]])
+    b = out["fp64"]
     ub = np.stack([b["ux"], b["uy"], b["uz"]])
-    err["u"] = float(np.linalg.norm(ua - ub) / np.linalg.norm(ub))
-    print("C5 5000 steps, FP32 vs FP64:", {k: f"{v:.2e}" for k, v in err.items()})
-    assert err["phi"] < 3e-3 and err["c"] < 2e-2 and err["u"] < 1e-3
+    for prec in ("fp32", "fp16"):
+        a = out[prec]
+        err = {k: float(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])) for k in ("phi", "c")}
+        ua = np.stack([a["ux"], a["uy"], a["uz"]])
+        err["u"] = float(np.linalg.norm(ua - ub) / np.linalg.norm(ub))
+        print(f"C5 5000 steps, {prec} vs FP64:", {k: f"{v:.2e}" for k, v in err.items()},
+              flush=True)
+        if prec == "fp32":
+            assert err["phi"] < 3e-3 and err["c"] < 2e-2 and err["u"] < 1e-3
+        else:
+            assert err["phi"] < 1e-2 and err["c"] < 5e-2 and err["u"] < 2e-3
