@@ -27,6 +27,14 @@ def _tiny(nx, ny, bc_y):
     return p, dict(phi=phi, c=c, ux=ux, uy=uy)
 
 
+def _shear_ratio():
+    """The Re = 1 shear drop with a density and viscosity ratio (drop:
+    rho 2, nu 0.05), started from a uniform pressure."""
+    p, fl = W.shear_drop(nx=200, ny=72, R=12.0, Ca=0.35, E=0.25, c0=0.3, Re=1.0)
+    p = dict(p, rho_a=2.0 * p["rho_b"], nu_a=0.5 * p["nu_b"])
+    return p, dict(fl, P=np.full_like(fl["phi"], p["rho_b"] / 3.0))
+
+
 CASES = {
     # static drop of Sec. 4.1 at the 128x128 scale, all 2000 steps
     "c1_static_drop": (lambda: W.static_drop(), 2000),
@@ -37,6 +45,7 @@ CASES = {
     # relative to u
     "shear_drop": (lambda: W.shear_drop(nx=200, ny=72, R=12.0, Ca=0.35, E=0.25, c0=0.3,
                                         Re=1.0), 200),
+    "shear_ratio": (_shear_ratio, 200),
     "coupled_random": (lambda: W.random_fields(136, 60, seed=3, amp=1.0, sigma0=2e-3,
                                                beta=0.3, u_wall=2e-2, M_phi=0.04,
                                                D_s=0.02), 150),
@@ -61,5 +70,11 @@ CASES = {
 
 # cases compared against the FP64 bar (1e-12) and cheap enough for the CPU
 # conditioning check
-FP64_CONDITIONING = ["ragged_periodic", "vortex", "shear_drop", "coupled_random",
+FP64_CONDITIONING = ["ragged_periodic", "vortex", "shear_drop", "shear_ratio", "coupled_random",
                      "density_ratio", "c3_full", "c2_full", "tiny_periodic", "tiny_walls"]
+
+# cases compared against the FP16 bar (1e-3), with their FP16 step counts:
+# a one-time relative perturbation of phi by one FP16 rounding (2.4e-4)
+# must not grow over the run
+FP16_CONDITIONING = [("c1_static_drop", 500), ("vortex", 400), ("shear_drop", 200),
+                     ("shear_ratio", 200)]

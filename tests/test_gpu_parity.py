@@ -65,6 +65,7 @@ PARITY = [
     ("ragged_periodic", "fp64"), ("ragged_periodic", "fp32"),
     ("vortex", "fp64"), ("vortex", "fp32"),
     ("shear_drop", "fp64"), ("shear_drop", "fp32"),
+    ("shear_ratio", "fp64"), ("shear_ratio", "fp32"),
     ("coupled_random", "fp64"),
     ("density_ratio", "fp64"),
     ("c2_full", "fp64"), ("c2_full", "fp32"),
@@ -101,7 +102,11 @@ def test_coupled_random_fp32(oracle_mod, gpu_lib):
     _parity(oracle_mod, p, fl, steps, "fp32", tol=3e-5)
 
 
-FP16_CASES = [("c1_static_drop", 500), ("vortex", 400), ("shear_drop", 200)]
+# FP16 cases damp a one-time phi perturbation of one FP16 rounding
+# (tests/test_parity_conditioning.py), so that 1e-3 measures the storage,
+# not an amplification the problem itself has
+FP16_CASES = [("c1_static_drop", 500), ("vortex", 400), ("shear_drop", 200),
+              ("shear_ratio", 200)]
 
 
 @pytest.mark.parametrize("name,steps", FP16_CASES)

@@ -67,7 +67,7 @@ PARITY3 = [("static3", "fp64"), ("static3", "fp32"), ("prescribed3", "fp64"),
            ("prescribed3", "fp32"), ("coupled3", "fp64"), ("coupled3", "fp32"),
            ("density3", "fp64"), ("shear3", "fp64"), ("shear3", "fp32"),
            ("static3", "fp16"), ("shear3", "fp16"), ("thin3", "fp64"), ("thin3", "fp32"),
-           ("tiny3", "fp64"), ("tiny3", "fp32")]
+           ("tiny3", "fp64"), ("tiny3", "fp32"), ("density3", "fp32"), ("density3", "fp16")]
 
 
 @pytest.mark.parametrize("name,prec", PARITY3)
