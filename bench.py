@@ -207,13 +207,14 @@ def cpu_baseline(sims, target_s=12.0):
     o.run(2)
     dt = time.perf_counter() - t0
     steps = 2
-    extra = max(0, int(target_s / max(dt / 2, 1e-6)) - 2)
-    extra = min(extra, 20000)
-    if extra:
+    # the first steps are slower (threads and pages warming up), so keep
+    # going in chunks sized from the running rate until target_s is reached
+    while dt < target_s and steps < 20000:
+        n = min(20000 - steps, max(1, int((target_s - dt) * steps / dt) + 1))
         t1 = time.perf_counter()
-        o.run(extra)
+        o.run(n)
         dt += time.perf_counter() - t1
-        steps += extra
+        steps += n
     nodes = p["nx"] * p["ny"] * p.get("nz", 1)
     size = "x".join(str(p[k]) for k in ("nx", "ny", "nz") if k in p)
     return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS",
