@@ -12,7 +12,9 @@ over every node of every simulation; populations stay resident in HBM.
 Prints one JSON line: coupled MLUPS, the step kernel's roofline fraction
 (algorithmic bytes over HIP-event-timed launches on the kernel's stream),
 the plain-copy ceiling measured in the same run (the library's copy with
-non-temporal loads and stores, 2 GiB buffers) and the step's fraction of it,
+non-temporal loads and stores, 2 GiB buffers; also with the buffers split
+into 27 planes copied side by side, the step's own number of streams) and
+the step's fraction of it,
 the other storage forms (FP64, FP16) of the batch, of the single 1024x512
 drop and of the 3D drop, and the CPU oracle timed on a bounded sample.
 
@@ -269,22 +271,38 @@ WORKLOADS = ("batched", "c3", "c1", "c2", "e1", "e2", "c5", "calib")
 FORM_WORKLOADS = ("batched", "c3", "c5")
 
 
-def copy_ceiling(torch, cmlb, stream, mib=2048, reps=20):
+def copy_ceiling(torch, cmlb, stream, mib=2048, reps=20, planes=None):
     """Read + write GB/s of the library's plain copy (non-temporal loads and
     stores) with two buffers of `mib` MiB: the practical HBM ceiling on the
-    device the benchmark runs on."""
+    device the benchmark runs on.  With `planes` (9 or 27) the buffers are
+    split into that many planes copied side by side (cmlb_copy_planes): the
+    same ceiling for a structure-of-arrays access with that many read and
+    write streams open at once."""
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    if planes:
+        # whole 4 KiB pages per plane, so that no plane starts inside a
+        # cache line (the populations' direction planes do not either)
+        plane_bytes = (4 * n // planes) // 4096 * 4096
+        moved = 2 * planes * plane_bytes
+
+        def run():
+            cmlb.device_copy_planes(a.data_ptr(), b.data_ptr(), plane_bytes, planes, True, stream)
+    else:
+        moved = 2 * 4 * n
+
+        def run():
+            cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, True, stream)
     for _ in range(3):
-        cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, True, stream)
+        run()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        cmlb.device_copy(a.data_ptr(), b.data_ptr(), 4 * n, True, stream)
+        run()
     e1.record()
     torch.cuda.synchronize()
-    gbps = 2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    gbps = moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     del a, b
     return gbps
 
@@ -442,6 +460,10 @@ def main():
                 key = f"{mib}MiB_lib_{'nt' if nt else 'default'}"
                 out[key] = round(2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9, 1)
             del a, b
+            # the same bytes as 9 and 27 planes copied side by side
+            for planes in (9, 27):
+                out[f"{mib}MiB_lib_nt_{planes}planes"] = round(
+                    copy_ceiling(torch, cmlb, stream, mib=mib, reps=reps, planes=planes), 1)
         print(json.dumps({"copy_GBps_read_plus_write": out}), flush=True)
         return
 
@@ -486,9 +508,10 @@ def main():
 
     # the plain-copy ceiling on this device, measured in the same run
     copy_gbps = copy_ceiling(torch, cmlb, stream)
+    copy27_gbps = copy_ceiling(torch, cmlb, stream, planes=27)
     traffic = traffic_entry(args.workload, prec, 3 if dim3 else 2)
-    log(f"[bench] copy ceiling {copy_gbps:.0f} GB/s: step at {achieved / copy_gbps:.3f} of it "
-        f"in algorithmic bytes")
+    log(f"[bench] copy ceiling {copy_gbps:.0f} GB/s (27 planes side by side: "
+        f"{copy27_gbps:.0f} GB/s): step at {achieved / copy_gbps:.3f} of it in algorithmic bytes")
 
     forms = {f"{args.workload}_{prec}": {"MLUPS": round(mlups, 1),
                                          "hbm_frac": round(achieved / HBM_PEAK_GBS, 4)}}
@@ -563,6 +586,15 @@ def main():
             "achieved_over_copy": round(achieved / copy_gbps, 4),
             "traffic_over_copy": (round(traffic / (ms_per_step / 1e3) / 1e9 / copy_gbps, 4)
                                   if traffic else None),
+            # the 2D coupled step reads and writes 27 direction planes
+            # (3 lattices x 9) at once
+            "planes27": {
+                "value": round(copy27_gbps, 1),
+                "kernel": "cmlb_copy_planes, 27 planes, non-temporal, two 2 GiB buffers",
+                "achieved_over": round(achieved / copy27_gbps, 4),
+                "traffic_over": (round(traffic / (ms_per_step / 1e3) / 1e9 / copy27_gbps, 4)
+                                 if traffic else None),
+            },
         },
         "cpu_baseline": cpu,
         "forms": forms,

@@ -215,6 +215,18 @@ int cmlb_set_tile_order(cmlb_ctx* ctx, int32_t group);
  * otherwise); the caller owns both buffers, which must not overlap. */
 int cmlb_copy(const void* src, void* dst, int64_t bytes, int32_t nontemporal, void* hip_stream);
 
+/* Measurement aid, not part of the method: the same copy in structure-of-
+ * arrays form.  src and dst each hold `planes` contiguous planes of
+ * plane_bytes (plane p at byte offset p * plane_bytes); one thread moves one
+ * 16-byte vector of every plane, all loads before the stores, so `planes`
+ * read and `planes` write streams are open at once, as in a step over 9 or 27
+ * direction planes.  planes must be 9 or 27; alignment, size, policy,
+ * ownership and error rules as for cmlb_copy; both buffers must hold
+ * planes * plane_bytes.  A plane_bytes that is not a multiple of the
+ * 128-byte cache line starts planes inside a line and costs bandwidth. */
+int cmlb_copy_planes(const void* src, void* dst, int64_t plane_bytes, int32_t planes,
+                     int32_t nontemporal, void* hip_stream);
+
 int64_t cmlb_step_count(const cmlb_ctx* ctx);
 int32_t cmlb_num_sims(const cmlb_ctx* ctx);
 /* Message of the last error on this context (owned by the context). */

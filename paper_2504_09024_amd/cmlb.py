@@ -44,7 +44,7 @@ EXPORTS = (
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
     "cmlb_set_use_graph",
     "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy", "cmlb_autotune",
-    "cmlb_copy", "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
+    "cmlb_copy", "cmlb_copy_planes", "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
 )
 
 EXPORTS3 = (
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
     ip = ctypes.POINTER(ctypes.c_int32)
     L.cmlb_autotune.argtypes = [vp, ctypes.c_int32, ip, ip, ip]
     L.cmlb_copy.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
+    L.cmlb_copy_planes.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp]
     L.cmlb_step_count.argtypes = [vp]
     L.cmlb_step_count.restype = ctypes.c_int64
     L.cmlb_num_sims.argtypes = [vp]
@@ -160,6 +161,19 @@ def device_copy(src_ptr: int, dst_ptr: int, nbytes: int, nontemporal: bool = Fal
                      1 if nontemporal else 0, ctypes.c_void_p(stream) if stream else None)
     if rc != 0:
         raise CmlbError(rc, "cmlb_copy")
+
+
+def device_copy_planes(src_ptr: int, dst_ptr: int, plane_bytes: int, planes: int,
+                       nontemporal: bool = False, stream=None) -> None:
+    """cmlb_copy_planes: the same copy over `planes` (9 or 27) contiguous
+    planes of plane_bytes, with one read and one write stream per plane open
+    at once.  A measurement aid, not part of the method."""
+    L = load()
+    rc = L.cmlb_copy_planes(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(plane_bytes),
+                            int(planes), 1 if nontemporal else 0,
+                            ctypes.c_void_p(stream) if stream else None)
+    if rc != 0:
+        raise CmlbError(rc, "cmlb_copy_planes")
 
 
 def _dptr(a):

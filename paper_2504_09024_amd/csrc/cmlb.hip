@@ -39,6 +39,23 @@ __global__ __launch_bounds__(256) void k_copy(const f32x4* __restrict__ a, f32x4
         }
     }
 }
+// Structure-of-arrays copy (cmlb_copy_planes): P planes of n4 vectors; each
+// thread loads one 16-byte vector of every plane, then stores them, so P read
+// and P write streams are open at once, as in a step over P direction planes.
+template <int P, bool NT>
+__global__ __launch_bounds__(256) void k_copy_planes(const f32x4* __restrict__ a,
+                                                     f32x4* __restrict__ b, int64_t n4) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n4) return;
+    f32x4 v[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q] = NT ? __builtin_nontemporal_load(&a[q * n4 + i]) : a[q * n4 + i];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        if (NT) __builtin_nontemporal_store(v[q], &b[q * n4 + i]);
+        else b[q * n4 + i] = v[q];
+    }
+}
 }  // namespace cmlb
 
 namespace {
@@ -951,6 +968,31 @@ int cmlb_copy(const void* src, void* dst, int64_t bytes, int32_t nontemporal, vo
         hipLaunchKernelGGL(cmlb::k_copy<true>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n4);
     else
         hipLaunchKernelGGL(cmlb::k_copy<false>, dim3((unsigned)blocks), dim3(256), 0, s, a, b, n4);
+    return hipGetLastError() == hipSuccess ? CMLB_OK : CMLB_EDEVICE;
+}
+
+int cmlb_copy_planes(const void* src, void* dst, int64_t plane_bytes, int32_t planes,
+                     int32_t nontemporal, void* hip_stream) {
+    if (!src || !dst || plane_bytes < 0 || (plane_bytes & 15) ||
+        (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15) ||
+        (planes != 9 && planes != 27) || (nontemporal != 0 && nontemporal != 1))
+        return CMLB_EINVAL;
+    const int64_t n4 = plane_bytes / 16;
+    if (n4 == 0) return CMLB_OK;
+    const int64_t blocks = (n4 + 255) / 256;
+    if (blocks > 0x7fffffff) return CMLB_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const auto* a = static_cast<const cmlb::f32x4*>(src);
+    auto* b = static_cast<cmlb::f32x4*>(dst);
+    const dim3 g((unsigned)blocks), t(256);
+    if (planes == 9 && nontemporal)
+        hipLaunchKernelGGL((cmlb::k_copy_planes<9, true>), g, t, 0, s, a, b, n4);
+    else if (planes == 9)
+        hipLaunchKernelGGL((cmlb::k_copy_planes<9, false>), g, t, 0, s, a, b, n4);
+    else if (nontemporal)
+        hipLaunchKernelGGL((cmlb::k_copy_planes<27, true>), g, t, 0, s, a, b, n4);
+    else
+        hipLaunchKernelGGL((cmlb::k_copy_planes<27, false>), g, t, 0, s, a, b, n4);
     return hipGetLastError() == hipSuccess ? CMLB_OK : CMLB_EDEVICE;
 }
 

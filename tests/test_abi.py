@@ -158,3 +158,18 @@ def test_copy_validation_before_device(lib):
     assert lib.cmlb_copy(vp(256), vp(512), -16, 0, None) == cmlb.EINVAL
     assert lib.cmlb_copy(vp(256), vp(512), 16, 2, None) == cmlb.EINVAL
     assert lib.cmlb_copy(vp(256), vp(512), 0, 1, None) == cmlb.OK
+
+
+def test_copy_planes_validation_before_device(lib):
+    """cmlb_copy_planes takes the rules of cmlb_copy and only 9 or 27
+    planes, checked before any device call."""
+    from paper_2504_09024_amd import cmlb
+    vp = ctypes.c_void_p
+    for planes in (0, 1, 8, 10, 26, 28, -9):
+        assert lib.cmlb_copy_planes(vp(256), vp(512), 16, planes, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy_planes(None, vp(256), 16, 9, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy_planes(vp(264), vp(512), 16, 9, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy_planes(vp(256), vp(512), 24, 27, 0, None) == cmlb.EINVAL
+    assert lib.cmlb_copy_planes(vp(256), vp(512), -16, 27, 1, None) == cmlb.EINVAL
+    assert lib.cmlb_copy_planes(vp(256), vp(512), 16, 27, 3, None) == cmlb.EINVAL
+    assert lib.cmlb_copy_planes(vp(256), vp(512), 0, 27, 1, None) == cmlb.OK

@@ -367,3 +367,21 @@ def test_device_copy(gpu_lib, nontemporal):
     torch.cuda.synchronize()
     assert torch.equal(b[:n], a)
     assert bool((b[n:] == -1.0).all())
+
+
+@pytest.mark.parametrize("planes,nontemporal", [(9, False), (27, True)])
+def test_device_copy_planes(gpu_lib, planes, nontemporal):
+    """cmlb_copy_planes copies every plane in full, with a ragged last
+    block, and nothing beyond the last plane."""
+    import torch
+    from paper_2504_09024_amd import cmlb
+    per = 256 * 1024 + 12  # float32 values per plane: 16-byte multiple, ragged tail
+    n = planes * per
+    a = torch.arange(n, dtype=torch.float32, device="cuda")
+    b = torch.full((n + 64,), -1.0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    cmlb.device_copy_planes(a.data_ptr(), b.data_ptr(), 4 * per, planes, nontemporal,
+                            torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(b[:n], a)
+    assert bool((b[n:] == -1.0).all())
