@@ -138,6 +138,17 @@ int cmlb_read_fields(cmlb_ctx* ctx, int32_t sim, double* phi, double* c, double*
  * Synchronises. */
 int cmlb_inventory(cmlb_ctx* ctx, int32_t sim, double* sum_phi, double* sum_c);
 
+/* Totals of phi and of c for the n simulations first .. first + n - 1 in
+ * one pair of launches (conservative forms of Eqs. CACE and ISS: the
+ * zeroth moments of f and h summed over the grid), into sums[2 n] (host,
+ * caller-owned): sums[2 i] = total phi and sums[2 i + 1] = total c of
+ * simulation first + i.  The order of every FP64 addition is fixed
+ * (per row, then rows in order), so each pair is bitwise equal to what
+ * cmlb_inventory returns for that simulation alone.  Synchronises.
+ * CMLB_EINVAL for an empty or out-of-range simulation range or a NULL
+ * sums. */
+int cmlb_inventories(cmlb_ctx* ctx, int32_t first, int32_t n, double* sums);
+
 /* Copy the populations of simulation `sim` to host (f, h, g each
  * [9][ny][nx] FP64, g ignored unless coupled; NULL skips).  Values are the
  * decoded pre-collision populations of the current step.  Synchronises. */

@@ -40,7 +40,7 @@ class SimParams(ctypes.Structure):
 
 EXPORTS = (
     "cmlb_create", "cmlb_init_fields", "cmlb_step", "cmlb_read_fields", "cmlb_inventory",
-    "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
+    "cmlb_inventories", "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
     "cmlb_set_use_graph",
     "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy", "cmlb_autotune",
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
     L.cmlb_step.argtypes = [vp, ctypes.c_int32]
     L.cmlb_read_fields.argtypes = [vp, ctypes.c_int32, dp, dp, dp, dp, dp]
     L.cmlb_inventory.argtypes = [vp, ctypes.c_int32, dp, dp]
+    L.cmlb_inventories.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp]
     L.cmlb_get_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
     L.cmlb_set_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
     L.cmlb_set_step_count.argtypes = [vp, ctypes.c_int64]
@@ -183,11 +184,18 @@ def _dptr(a):
 
 
 def _f64(a, shape):
+    """An FP64 C-ordered copy of `a`, which must have exactly `shape` or be
+    flat with that many elements (a transposed or otherwise reshaped array
+    would scramble the nodes, so any other shape raises ValueError)."""
     if a is None:
         return None
     arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
-    if arr.shape != shape:
-        arr = arr.reshape(shape)
+    if arr.shape != tuple(shape):
+        if arr.ndim == 1 and arr.size == int(np.prod(shape)):
+            arr = arr.reshape(shape)
+        else:
+            raise ValueError(f"array of shape {arr.shape} where {tuple(shape)} (or flat) is "
+                             "expected")
     return arr
 
 
@@ -276,6 +284,15 @@ class Context:
         self._check(self.L.cmlb_inventory(self.h, sim, ctypes.byref(a), ctypes.byref(b)),
                     "cmlb_inventory")
         return a.value, b.value
+
+    def inventories(self, first=0, n=None):
+        """cmlb_inventories: (total phi, total c) of simulations first ..
+        first + n - 1 (all from `first` when n is None), as an (n, 2) array."""
+        n = len(self.shapes) - first if n is None else int(n)
+        out = np.zeros((max(n, 0), 2))
+        self._check(self.L.cmlb_inventories(self.h, int(first), n, _dptr(out)),
+                    "cmlb_inventories")
+        return out
 
     def get_populations(self, sim=0):
         ny, nx = self.shapes[sim]

@@ -137,8 +137,8 @@ struct cmlb_ctx {
     int64_t* d_step = nullptr;  // [2]
     int32_t* d_fault = nullptr; // [n_sims]
     double* d_stage = nullptr;  // staging: max(27, 5) * max_plane doubles
-    double* d_rows = nullptr;   // inventory row partials
-    double* d_inv = nullptr;    // [2]
+    double* d_rows = nullptr;   // inventory row partials: 2 per row of every sim
+    double* d_inv = nullptr;    // inventory totals: 2 per sim
     int cur = 0;                // population/counter parity holding the current state
     int64_t step = 0;
     int tile_rows = 0;          // 0 = default
@@ -433,15 +433,39 @@ void launch_encode(cmlb_ctx* c, int sim) {
                        c->stream, (void*)base, (const SimDev*)(c->d_sims + sim), c->nlat,
                        c->walls, (const double*)c->d_stage);
 }
+// Inventories of simulations [first, first + n): row partials into `rows`
+// (two doubles per row of those simulations), totals into out[2 n].
 template <class S>
-void launch_inventory(cmlb_ctx* c, int sim) {
-    const SimDev& d = c->sims[sim];
-    const char* base = static_cast<const char*>(c->pop[c->cur]) + d.off * (int64_t)sizeof(S);
-    hipLaunchKernelGGL(k_inventory_rows<S>, dim3(d.ny), dim3(WG), 0, c->stream,
-                       (const void*)base, (const SimDev*)(c->d_sims + sim), c->d_rows);
-    hipLaunchKernelGGL(k_inventory_final, dim3(1), dim3(64), 0, c->stream,
-                       (const double*)c->d_rows, d.ny, c->d_inv);
+void launch_inventory_s(cmlb_ctx* c, int first, int n, int max_ny, double* rows, double* out) {
+    const int row_base = c->sims[first].row0;
+    hipLaunchKernelGGL(k_inventory_rows<S>, dim3((unsigned)((int64_t)n * max_ny)), dim3(WG), 0,
+                       c->stream,
+                       (const void*)c->pop[c->cur], (const SimDev*)c->d_sims, first, max_ny,
+                       row_base, rows);
+    hipLaunchKernelGGL(k_inventory_final, dim3((n + 63) / 64), dim3(64), 0, c->stream,
+                       (const double*)rows, (const SimDev*)c->d_sims, first, n, row_base, out);
 }
+int launch_inventory(cmlb_ctx* c, int first, int n, double* rows, double* out) {
+    int max_ny = 0;
+    for (int s = first; s < first + n; ++s) max_ny = std::max(max_ny, c->sims[s].ny);
+    if ((int64_t)n * max_ny > (int64_t)INT32_MAX)
+        return fail(c, CMLB_EINVAL, "too many simulation rows for one inventory launch");
+    if (c->prec == CMLB_FP64)
+        launch_inventory_s<double>(c, first, n, max_ny, rows, out);
+    else if (c->prec == CMLB_FP32)
+        launch_inventory_s<float>(c, first, n, max_ny, rows, out);
+    else
+        launch_inventory_s<_Float16>(c, first, n, max_ny, rows, out);
+    HIP_TRY(c, hipGetLastError());
+    return CMLB_OK;
+}
+// rows of the simulations [first, first + n)
+int64_t rows_of_range(const cmlb_ctx* c, int first, int n) {
+    int64_t r = 0;
+    for (int s = first; s < first + n; ++s) r += c->sims[s].ny;
+    return r;
+}
+
 template <class S, class T>
 void launch_init(cmlb_ctx* c, int sim, const InitArgs& a) {
     const SimDev& d = c->sims[sim];
@@ -483,7 +507,7 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
     if (bc != CMLB_BC_PERIODIC && bc != CMLB_BC_MOVING_WALLS) return CMLB_EINVAL;
     const int nlat = flow == CMLB_FLOW_COUPLED ? 3 : 2;
     std::vector<SimDev> sims(n_sims);
-    int64_t off = 0, uoff = 0, max_plane = 0, node_count = 0;
+    int64_t off = 0, uoff = 0, max_plane = 0, node_count = 0, row_count = 0;
     int max_ny = 0;
     for (int s = 0; s < n_sims; ++s) {
         const cmlb_sim_params& p = params[s];
@@ -550,6 +574,9 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
         if ((int64_t)9 * plane * (int64_t)storage_bytes(precision) > (int64_t)INT32_MAX)
             return CMLB_EINVAL;  // a lattice must fit a 32-bit buffer range
         d.node_base = (uint32_t)node_count;
+        if (row_count + p.ny > (int64_t)INT32_MAX) return CMLB_EINVAL;
+        d.row0 = (int32_t)row_count;
+        row_count += p.ny;
         d.uniform_rho = p.rho_a == p.rho_b;
         d.uniform_nu = p.nu_a == p.nu_b;
         fill_consts(d.kd, d);
@@ -600,8 +627,9 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
     if (hipMalloc(&c->d_fault, sizeof(int32_t) * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_stage, sizeof(double) * 27 * max_plane) != hipSuccess)
         return bail(CMLB_ENOMEM);
-    if (hipMalloc(&c->d_rows, sizeof(double) * 2 * max_ny) != hipSuccess) return bail(CMLB_ENOMEM);
-    if (hipMalloc(&c->d_inv, sizeof(double) * 2) != hipSuccess) return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_rows, sizeof(double) * 2 * row_count) != hipSuccess)
+        return bail(CMLB_ENOMEM);
+    if (hipMalloc(&c->d_inv, sizeof(double) * 2 * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
     if (hipMemset(c->pop[0], 0, sb * off) != hipSuccess) return bail(CMLB_EDEVICE);
     if (hipMemset(c->pop[1], 0, sb * off) != hipSuccess) return bail(CMLB_EDEVICE);
     if (hipMemset(c->d_step, 0, sizeof(int64_t) * 2) != hipSuccess) return bail(CMLB_EDEVICE);
@@ -717,18 +745,26 @@ int cmlb_read_fields(cmlb_ctx* c, int32_t sim, double* phi, double* cc, double* 
 int cmlb_inventory(cmlb_ctx* c, int32_t sim, double* sum_phi, double* sum_c) {
     if (!c) return CMLB_EINVAL;
     if (!check_sim(c, sim)) return fail(c, CMLB_EINVAL, "bad simulation index");
-    if (c->prec == CMLB_FP64)
-        launch_inventory<double>(c, sim);
-    else if (c->prec == CMLB_FP32)
-        launch_inventory<float>(c, sim);
-    else
-        launch_inventory<_Float16>(c, sim);
-    HIP_TRY(c, hipGetLastError());
+    int rc = launch_inventory(c, sim, 1, c->d_rows, c->d_inv);
+    if (rc != CMLB_OK) return rc;
     double v[2];
     HIP_TRY(c, hipMemcpyAsync(v, c->d_inv, sizeof(v), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (sum_phi) *sum_phi = v[0];
     if (sum_c) *sum_c = v[1];
+    return CMLB_OK;
+}
+
+int cmlb_inventories(cmlb_ctx* c, int32_t first, int32_t n, double* sums) {
+    if (!c) return CMLB_EINVAL;
+    if (!sums || first < 0 || n < 1 || first > c->n_sims - n)
+        return fail(c, CMLB_EINVAL, "bad simulation range [%d, %d + %d) or null output", first,
+                    first, n);
+    int rc = launch_inventory(c, first, n, c->d_rows, c->d_inv);
+    if (rc != CMLB_OK) return rc;
+    HIP_TRY(c, hipMemcpyAsync(sums, c->d_inv, sizeof(double) * 2 * n, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return CMLB_OK;
 }
 

@@ -642,17 +642,25 @@ __global__ __launch_bounds__(WG) void k_encode(void* pop, const SimDev* sd, int 
 }
 
 // ---------------------------------------------------------------------------
-// Inventories: FP64 totals of phi and c.  One workgroup per row; each
-// thread sums its columns in order, then a fixed butterfly over the wave
-// and a fixed order over the waves; a second kernel sums the rows in order.
-// The result does not depend on the step kernel's tiling.
+// Inventories: FP64 totals of phi and c for the simulations [first, first+n)
+// of a context in two launches.  Stage 1 has one workgroup per (simulation,
+// row), workgroup index = (sim - first) * max_ny + row: each thread sums its columns in order, then a fixed butterfly over
+// the wave and a fixed order over the waves give the row's partial, stored
+// at index row0 - row_base + y.  Stage 2 has one thread per simulation,
+// which adds that simulation's row partials in row order.  The order of
+// every addition is fixed, so a total does not depend on the step kernel's
+// tiling, on which other simulations share the launch, or on the buffer the
+// partials go to.
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const SimDev* sd,
+__global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const SimDev* sims,
+                                                       int first, int max_ny, int row_base,
                                                        double* rows) {
+    const SimDev* sd = sims + first + (int)(blockIdx.x / max_ny);
     const int nx = sd->nx, ny = sd->ny, plane = nx * ny;
-    const int y = blockIdx.x;
-    const S* p = static_cast<const S*>(pop);
+    const int y = (int)(blockIdx.x % max_ny);
+    if (y >= ny) return;
+    const S* p = static_cast<const S*>(pop) + sd->off;
     const double inv_f = 1.0 / sd->scale_f, inv_h = 1.0 / sd->scale_h, qref = sd->qref_f;
     double sf = 0.0, sh = 0.0;
     for (int x = threadIdx.x; x < nx; x += WG) {
@@ -682,20 +690,26 @@ __global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const Si
             a += red[0][w];
             b += red[1][w];
         }
-        rows[2 * y] = a;
-        rows[2 * y + 1] = b;
+        const int r = sd->row0 - row_base + y;
+        rows[2 * r] = a;
+        rows[2 * r + 1] = b;
     }
 }
 
-__global__ void k_inventory_final(const double* rows, int ny, double* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_inventory_final(const double* rows, const SimDev* sims,
+                                                        int first, int n, int row_base,
+                                                        double* out) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= n) return;
+    const SimDev* sd = sims + first + i;
+    const int r0 = sd->row0 - row_base;
     double a = 0.0, b = 0.0;
-    for (int y = 0; y < ny; ++y) {
-        a += rows[2 * y];
-        b += rows[2 * y + 1];
+    for (int y = 0; y < sd->ny; ++y) {
+        a += rows[2 * (r0 + y)];
+        b += rows[2 * (r0 + y) + 1];
     }
-    out[0] = a;
-    out[1] = b;
+    out[2 * i] = a;
+    out[2 * i + 1] = b;
 }
 
 }  // namespace cmlb

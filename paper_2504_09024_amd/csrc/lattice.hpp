@@ -60,7 +60,7 @@ struct SimDev {
     int64_t ushape_off;     // element offset of the prescribed-velocity shapes
     uint32_t node_base;     // first global node index (random streams)
     int32_t uniform_rho, uniform_nu;
-    int32_t pad_;
+    int32_t row0;           // rows of all earlier simulations (inventory partials)
     double W, phi_a, phi_b, inv_dphi, phim;
     double theta_k, thetac_k;  // 4/W and 8/W
     double M_phi, D_s, omega_k, omega_c;

@@ -385,3 +385,35 @@ def test_device_copy_planes(gpu_lib, planes, nontemporal):
     torch.cuda.synchronize()
     assert torch.equal(b[:n], a)
     assert bool((b[n:] == -1.0).all())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_inventories_batched_match_single(oracle_mod, gpu_lib, prec):
+    """cmlb_inventories over a ragged batch in one pair of launches: every
+    simulation's totals are bitwise those of cmlb_inventory alone, whatever
+    range of the batch shares the launch; in FP64 they match the oracle's
+    totals of the same state (conservative forms of Eqs. CACE and ISS)."""
+    cases = [W.shear_drop(nx=nx, ny=ny, R=ny / 8, Ca=ca, E=e, c0=c0)
+             for nx, ny, ca, e, c0 in ((128, 64, 0.2, 0.1, 0.2), (200, 96, 0.5, 0.4, 0.4),
+                                       (64, 48, 0.1, 0.3, 0.1), (100, 70, 0.3, 0.2, 0.3))]
+    ps = [c[0] for c in cases]
+    fls = [c[1] for c in cases]
+    ctx = gpu_ctx(ps, fls, prec)
+    ctx.step(17)
+    single = np.array([ctx.inventory(i) for i in range(4)])
+    allv = ctx.inventories()
+    assert allv.shape == (4, 2)
+    assert np.array_equal(allv, single)
+    assert np.array_equal(ctx.inventories(1, 2), single[1:3])
+    assert np.array_equal(ctx.inventories(3, 1), single[3:4])
+    if prec == "fp64":
+        for i in range(4):
+            f, h, _ = ctx.get_populations(i)
+            tot = (f.sum(), h.sum())
+            assert abs(allv[i, 0] - tot[0]) <= 1e-12 * abs(tot[0])
+            assert abs(allv[i, 1] - tot[1]) <= 1e-12 * abs(tot[1])
+    from paper_2504_09024_amd import cmlb
+    for first, n in ((-1, 1), (0, 0), (3, 2), (4, 1)):
+        with pytest.raises(cmlb.CmlbError):
+            ctx.inventories(first, n)
+    ctx.close()
