@@ -149,6 +149,28 @@ int cmlb_inventory(cmlb_ctx* ctx, int32_t sim, double* sum_phi, double* sum_c);
  * sums. */
 int cmlb_inventories(cmlb_ctx* ctx, int32_t first, int32_t n, double* sums);
 
+/* Rows of the largest simulation range cmlb_inventories_noalloc accepts. */
+#define CMLB_NOALLOC_MAX_ROWS 65536
+
+/* Allocation-free form of cmlb_inventories, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It enqueues the same two
+ * launches on the context's stream and returns without synchronising; it
+ * calls no hipMalloc, hipFree or other allocating routine and copies
+ * nothing to the host.  The totals go to d_sums, DEVICE memory of 2 n
+ * doubles owned by the caller and 8-byte aligned, laid out as in
+ * cmlb_inventories and bitwise equal to its results.  The row partials go
+ * to a scratch array that the library holds in static device memory, one
+ * per GPU (1 MiB, kept until the process ends): the simulations of the
+ * range may hold at most CMLB_NOALLOC_MAX_ROWS rows in total (CMLB_EINVAL
+ * with a message otherwise).  Every call on one GPU shares that GPU's
+ * array, and each call overwrites the partials it uses before reading
+ * them; calls whose launches overlap on one GPU (other streams, other
+ * contexts or threads) race on it and must be ordered by the caller.
+ * CMLB_EINVAL also for a bad range or a NULL or misaligned d_sums;
+ * CMLB_EDEVICE if the array's device address could not be obtained. */
+int cmlb_inventories_noalloc(cmlb_ctx* ctx, int32_t first, int32_t n, double* d_sums);
+
 /* Copy the populations of simulation `sim` to host (f, h, g each
  * [9][ny][nx] FP64, g ignored unless coupled; NULL skips).  Values are the
  * decoded pre-collision populations of the current step.  Synchronises. */

@@ -40,7 +40,7 @@ class SimParams(ctypes.Structure):
 
 EXPORTS = (
     "cmlb_create", "cmlb_init_fields", "cmlb_step", "cmlb_read_fields", "cmlb_inventory",
-    "cmlb_inventories", "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
+    "cmlb_inventories", "cmlb_inventories_noalloc", "cmlb_get_populations", "cmlb_set_populations", "cmlb_set_step_count", "cmlb_fault_flags",
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
     "cmlb_set_use_graph",
     "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy", "cmlb_autotune",
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     L.cmlb_read_fields.argtypes = [vp, ctypes.c_int32, dp, dp, dp, dp, dp]
     L.cmlb_inventory.argtypes = [vp, ctypes.c_int32, dp, dp]
     L.cmlb_inventories.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp]
+    L.cmlb_inventories_noalloc.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp]
     L.cmlb_get_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
     L.cmlb_set_populations.argtypes = [vp, ctypes.c_int32, dp, dp, dp]
     L.cmlb_set_step_count.argtypes = [vp, ctypes.c_int64]
@@ -293,6 +294,15 @@ class Context:
         self._check(self.L.cmlb_inventories(self.h, int(first), n, _dptr(out)),
                     "cmlb_inventories")
         return out
+
+    def inventories_noalloc(self, d_sums, first=0, n=None):
+        """cmlb_inventories_noalloc: enqueue the totals of simulations first ..
+        first + n - 1 into device memory at address `d_sums` (2 n doubles,
+        caller-owned); asynchronous, allocates nothing."""
+        n = len(self.shapes) - first if n is None else int(n)
+        self._check(self.L.cmlb_inventories_noalloc(self.h, int(first), n,
+                                                     ctypes.c_void_p(int(d_sums))),
+                    "cmlb_inventories_noalloc")
 
     def get_populations(self, sim=0):
         ny, nx = self.shapes[sim]

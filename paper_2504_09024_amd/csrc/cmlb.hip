@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,42 @@ __global__ __launch_bounds__(256) void k_copy_planes(const f32x4* __restrict__ a
 }  // namespace cmlb
 
 namespace {
+
+// Scratch of the allocation-free inventory entry point
+// (cmlb_inventories_noalloc): the row partials live in this file-scope
+// device array, one copy per GPU, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in): the device address is looked up once per device with
+// hipGetSymbolAddress at context creation and used from then on.
+constexpr int SCRATCH_ROWS = CMLB_NOALLOC_MAX_ROWS;
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[2 * SCRATCH_ROWS];
+
+namespace {
+
+// Device address of `scratch` on the current device `device` (looked up
+// once per device; nullptr if the lookup failed, the error in *err).
+void* scratch_on(int device, hipError_t* err) {
+    *err = hipErrorInvalidDevice;
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && p)
+            g_scratch_ptr[device] = p;
+        else
+            g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    *err = g_scratch_err[device];
+    return g_scratch_ptr[device];
+}
 
 constexpr int GRAPH_PAIRS = 8;  // a graph holds 2 * GRAPH_PAIRS steps
 
@@ -139,6 +176,8 @@ struct cmlb_ctx {
     double* d_stage = nullptr;  // staging: max(27, 5) * max_plane doubles
     double* d_rows = nullptr;   // inventory row partials: 2 per row of every sim
     double* d_inv = nullptr;    // inventory totals: 2 per sim
+    void* scratch = nullptr;    // this device's scratch array (allocation-free entry point)
+    hipError_t scratch_err = hipSuccess;
     int cur = 0;                // population/counter parity holding the current state
     int64_t step = 0;
     int tile_rows = 0;          // 0 = default
@@ -630,6 +669,7 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
     if (hipMalloc(&c->d_rows, sizeof(double) * 2 * row_count) != hipSuccess)
         return bail(CMLB_ENOMEM);
     if (hipMalloc(&c->d_inv, sizeof(double) * 2 * n_sims) != hipSuccess) return bail(CMLB_ENOMEM);
+    c->scratch = scratch_on(c->device, &c->scratch_err);
     if (hipMemset(c->pop[0], 0, sb * off) != hipSuccess) return bail(CMLB_EDEVICE);
     if (hipMemset(c->pop[1], 0, sb * off) != hipSuccess) return bail(CMLB_EDEVICE);
     if (hipMemset(c->d_step, 0, sizeof(int64_t) * 2) != hipSuccess) return bail(CMLB_EDEVICE);
@@ -766,6 +806,25 @@ int cmlb_inventories(cmlb_ctx* c, int32_t first, int32_t n, double* sums) {
                               c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return CMLB_OK;
+}
+
+int cmlb_inventories_noalloc(cmlb_ctx* c, int32_t first, int32_t n, double* d_sums) {
+    if (!c) return CMLB_EINVAL;
+    if (!d_sums || (reinterpret_cast<uintptr_t>(d_sums) & 7) || first < 0 || n < 1 ||
+        first > c->n_sims - n)
+        return fail(c, CMLB_EINVAL,
+                    "bad simulation range [%d, %d + %d) or null / misaligned device output",
+                    first, first, n);
+    const int64_t rows = rows_of_range(c, first, n);
+    if (rows > SCRATCH_ROWS)
+        return fail(c, CMLB_EINVAL,
+                    "simulations [%d, %d) hold %lld rows, more than the %d rows of the scratch "
+                    "array (CMLB_NOALLOC_MAX_ROWS)",
+                    first, first + n, (long long)rows, SCRATCH_ROWS);
+    if (!c->scratch)
+        return fail(c, CMLB_EDEVICE, "device address of the scratch array unavailable: %s",
+                    hipGetErrorString(c->scratch_err));
+    return launch_inventory(c, first, n, static_cast<double*>(c->scratch), d_sums);
 }
 
 int cmlb_get_populations(cmlb_ctx* c, int32_t sim, double* f, double* h, double* g) {
