@@ -103,7 +103,10 @@ typedef struct cmlb_ctx cmlb_ctx;
  * precision is a cmlb_precision.  hip_stream is a hipStream_t (NULL: the
  * library creates and owns one).  Device buffers: two copies of every
  * population set (f, h, and g when coupled) plus small per-tile tables.
- * On failure *out is NULL. */
+ * One simulation's populations (rows padded to multiples of 64 nodes) must
+ * fit 2^31 bytes: 27 or 18 values per node of 8, 4 or 2 bytes (CMLB_EINVAL
+ * otherwise; e.g. at most 19.9 M nodes for FP32 coupled flow).  On failure
+ * *out is NULL. */
 int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision,
                 void* hip_stream, cmlb_ctx** out);
 

@@ -479,8 +479,8 @@ void launch_inventory_s(cmlb_ctx* c, int first, int n, int max_ny, double* rows,
     const int row_base = c->sims[first].row0;
     hipLaunchKernelGGL(k_inventory_rows<S>, dim3((unsigned)((int64_t)n * max_ny)), dim3(WG), 0,
                        c->stream,
-                       (const void*)c->pop[c->cur], (const SimDev*)c->d_sims, first, max_ny,
-                       row_base, rows);
+                       (const void*)c->pop[c->cur], (const SimDev*)c->d_sims, c->nlat, first,
+                       max_ny, row_base, rows);
     hipLaunchKernelGGL(k_inventory_final, dim3((n + 63) / 64), dim3(64), 0, c->stream,
                        (const double*)rows, (const SimDev*)c->d_sims, first, n, row_base, out);
 }
@@ -610,8 +610,11 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
             d.qref_f = 0.0;
             d.scale_f = d.scale_h = d.scale_g = 1.0;
         }
-        if ((int64_t)9 * plane * (int64_t)storage_bytes(precision) > (int64_t)INT32_MAX)
-            return CMLB_EINVAL;  // a lattice must fit a 32-bit buffer range
+        // a simulation's population block (rows padded to whole runs of 64
+        // nodes) must fit a 32-bit buffer range
+        const int64_t nbx = (p.nx + 63) / 64;
+        const int64_t row_bytes = nbx * nlat * 9 * 64 * (int64_t)storage_bytes(precision);
+        if (row_bytes * p.ny > (int64_t)INT32_MAX) return CMLB_EINVAL;
         d.node_base = (uint32_t)node_count;
         if (row_count + p.ny > (int64_t)INT32_MAX) return CMLB_EINVAL;
         d.row0 = (int32_t)row_count;
@@ -622,7 +625,7 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
         fill_consts(d.kf, d);
         sims[s] = d;
         node_count += plane;
-        off += (int64_t)nlat * 9 * plane;
+        off += (int64_t)nlat * 9 * 64 * nbx * p.ny;  // rows padded to whole runs
         if (flow == CMLB_FLOW_PRESCRIBED) uoff += 2 * plane;
         max_plane = std::max(max_plane, plane);
         max_ny = std::max(max_ny, p.ny);

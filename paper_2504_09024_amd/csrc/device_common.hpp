@@ -18,9 +18,10 @@ struct Store<_Float16> {
 };
 
 // ---------------------------------------------------------------------------
-// Storage access through buffer descriptors: one descriptor per lattice, the
-// node offset in a VGPR and the direction plane in the SGPR offset, so the 27
-// loads and stores of a node share one address computation.  Out-of-range
+// Storage access through buffer descriptors: the node offset in a VGPR and
+// the direction's offset in the SGPR offset, so the loads and stores of a
+// node share one address computation (`gload` reads through a plain 64-bit
+// address instead, for paths whose offsets vary per load).  Out-of-range
 // buffer accesses return 0 / are dropped by the hardware.  `load` returns
 // the stored value in the compute type; `raw` returns it as a register word
 // (binary16 zero-extended to 32 bits, one value per register) for `widen` to
@@ -51,6 +52,9 @@ struct Buf<double> {
     static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return raw(r, vo, so);
     }
+    static __device__ __forceinline__ double gload(const char* p) {
+        return *reinterpret_cast<const double*>(p);
+    }
     template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, double v,
                                                  uint32_t) {
@@ -66,6 +70,9 @@ struct Buf<float> {
     }
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return raw(r, vo, so);
+    }
+    static __device__ __forceinline__ float gload(const char* p) {
+        return *reinterpret_cast<const float*>(p);
     }
     template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,
@@ -91,6 +98,9 @@ struct Buf<_Float16> {
     }
     static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
         return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)));
+    }
+    static __device__ __forceinline__ float gload(const char* p) {
+        return float(*reinterpret_cast<const _Float16*>(p));
     }
     template <int CP>
     static __device__ __forceinline__ void store(__amdgpu_buffer_rsrc_t r, int vo, int so, float v,

@@ -73,57 +73,65 @@ __device__ __forceinline__ Raw6<T> moments6_nc(const T d[9]) {
     return raw_moments6(d);
 }
 
-template <class S, class T>
-__device__ __forceinline__ void load9(__amdgpu_buffer_rsrc_t r, int vo, int pb, T v[9]) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) v[a] = T(Buf<S>::load(r, vo, a * pb));
-}
-// g: deviations d_a = w_a s_a / scale
-template <class S, class T>
-__device__ __forceinline__ void load9_dev(__amdgpu_buffer_rsrc_t r, int vo, int pb, T inv, T d[9]) {
-#pragma clang fp contract(off)
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const T s = T(Buf<S>::load(r, vo, a * pb));
-        d[a] = Store<S>::scaled ? wgt<T>(a) * (s * inv) : wgt<T>(a) * s;
-    }
+// ---------------------------------------------------------------------------
+// Population layout in HBM.  A simulation's populations are kept in runs of
+// 64 consecutive nodes of one grid row, the nodes one wavefront covers: run
+// r = y * nbx + x / 64 with nbx = ceil(nx / 64).  A run's block holds its
+// NL * 9 direction vectors of 64 values one after another, lattice-major:
+//     element(lat, q, x, y) = ((r * NL + lat) * 9 + q) * 64 + x mod 64,
+// so a wavefront reads and writes one contiguous block per grid row instead
+// of NL * 9 planes far apart.  Rows are padded to whole runs (padding slots
+// are never read).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t pelem(int lat, int q, int x, int y, int nbx, int nl) {
+    return ((((int64_t)y * nbx + (x >> 6)) * nl + lat) * 9 + q) * 64 + (x & 63);
 }
 
 // ---------------------------------------------------------------------------
-// Pulled loads.  For a node whose nine sources x - e_a lie in rows of the
-// grid, the source shift goes into the scalar offset: so[a] = a*plane -
-// (e_ax + e_ay nx), in bytes (non-negative for a >= 1 because a plane holds
-// at least four rows), and the node offset is shared by all nine loads.  The
-// periodic wrap in x stays on this path: a node in column 0 pulls the
-// directions with e_ax = +1 from column nx - 1 (node offset + nx), a node in
-// column nx - 1 those with e_ax = -1 from column 0 (- nx); xp and xm carry
-// these per-lane corrections.  Near a wall, or on grids narrower than a
-// tile plus its halo, the sources wrap or come from the node's own opposite
-// slot on the general path.
+// Pulled loads.  Each lattice has a buffer descriptor that starts at its
+// direction 0 in the simulation's first run block, so a value's byte offset
+// is r * BLK + a * RUN + (x mod 64) * SB (BLK bytes per run block, RUN per
+// direction vector of a run); a simulation's block must fit a 32-bit range.
+// On the fast path a node's loads use three vector offsets, the offsets of
+// its source columns in row y - 1: vo for x (directions with e_ax = 0), xp
+// for x - 1 (e_ax = +1; the previous run for lane 0 of a run, column nx - 1
+// at x = 0) and xm for x + 1 (e_ax = -1; the next run for lane 63, column 0
+// at x = nx - 1).  Direction a adds a * RUN, a constant the compiler folds
+// into the instruction's offset field, and the scalar offset (1 - e_ay) * RB
+// (RB bytes per grid row), one of three values.  No offset is negative (a
+// raw buffer access whose vector offset wraps below zero reads as out of
+// range): the fast path serves rows y >= 1 only.  Near a wall or the y wrap,
+// or on grids narrower than a tile plus its halo, the general path folds
+// each source (wrap, or the node's own opposite slot at a wall) and
+// computes each load's offset on its own.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void pull_offsets(int pb, int nx, int sb, int so[9]) {
-#pragma unroll
-    for (int a = 0; a < 9; ++a) so[a] = a * pb - (EXa(a) + EYa(a) * nx) * sb;
+template <int SB>
+__device__ __forceinline__ void run_offsets(int x, int y, int nx, int nbx, int blk, int& vo,
+                                            int& xp, int& xm) {
+    const int r = (y - 1) * nbx;
+    const int xl = x == 0 ? nx - 1 : x - 1;
+    const int xr = x == nx - 1 ? 0 : x + 1;
+    vo = (r + (x >> 6)) * blk + (x & 63) * SB;
+    xp = (r + (xl >> 6)) * blk + (xl & 63) * SB;
+    xm = (r + (xr >> 6)) * blk + (xr & 63) * SB;
 }
 
 template <class S, class T>
 __device__ __forceinline__ void pull9_inner(__amdgpu_buffer_rsrc_t r, int vo, int xp, int xm,
-                                            const int so[9], T v[9]) {
+                                            int row_bytes, T v[9]) {
+    constexpr int RUN = 64 * (int)sizeof(S);
 #pragma unroll
-    for (int a = 0; a < 9; ++a)
-        v[a] = T(Buf<S>::load(r, EXa(a) > 0 ? xp : (EXa(a) < 0 ? xm : vo), so[a]));
-}
-// node offset of column x in row y and its two wrap-corrected forms
-template <int SB>
-__device__ __forceinline__ void wrap_offsets(int x, int y, int nx, int& vo, int& xp, int& xm) {
-    vo = (y * nx + x) * SB;
-    xp = x == 0 ? vo + nx * SB : vo;
-    xm = x == nx - 1 ? vo - nx * SB : vo;
+    for (int a = 0; a < 9; ++a) {
+        const int voff = (EXa(a) > 0 ? xp : (EXa(a) < 0 ? xm : vo)) + a * RUN;
+        const int soff = EYa(a) > 0 ? 0 : (EYa(a) == 0 ? row_bytes : 2 * row_bytes);
+        v[a] = T(Buf<S>::load(r, voff, soff));
+    }
 }
 
 template <class S, class T, bool WALLS>
-__device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int pb, int lx, int ly,
-                                           int nx, int ny, T v[9]) {
+__device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int lx, int ly, int nx,
+                                           int ny, int nbx, int blk, T v[9]) {
+    constexpr int RUN = 64 * (int)sizeof(S);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         int sx = lx - EXa(a), sy = ly - EYa(a), pa = a;
@@ -138,10 +146,10 @@ __device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int pb, int
                 sy = sy < 0 ? sy + ny : sy - ny;
             }
         }
-        // the plane varies per lane here (bounce-back), so its offset goes
-        // into the vector offset: a per-lane scalar offset would make the
-        // compiler loop over the distinct values
-        v[a] = T(Buf<S>::load(r, (sy * nx + sx) * (int)sizeof(S) + pa * pb, 0));
+        // the direction varies per lane here (bounce-back), so it goes into
+        // the vector offset
+        v[a] = T(Buf<S>::load(r, (sy * nbx + (sx >> 6)) * blk + pa * RUN + (sx & 63) * (int)sizeof(S),
+                              0));
     }
 }
 
@@ -153,10 +161,12 @@ __device__ __forceinline__ void to_dev(T v[9], T inv) {
     for (int a = 0; a < 9; ++a) v[a] = Store<S>::scaled ? wgt<T>(a) * (v[a] * inv) : wgt<T>(a) * v[a];
 }
 
-// Slot from which node (x, y) pulls direction a: (plane, node index).
+// Slot from which node (x, y) pulls direction a: (direction plane, source
+// column, source row).
 __device__ __forceinline__ void pull_slot(int x, int y, int a, int nx, int ny, bool walls,
-                                          int& plane_a, int& node) {
-    int sx = x - EXa(a), sy = y - EYa(a);
+                                          int& plane_a, int& sx, int& sy) {
+    sx = x - EXa(a);
+    sy = y - EYa(a);
     plane_a = a;
     if (sx < 0) sx += nx;
     else if (sx >= nx) sx -= nx;
@@ -169,7 +179,6 @@ __device__ __forceinline__ void pull_slot(int x, int y, int a, int nx, int ny, b
             sy = sy < 0 ? sy + ny : sy - ny;
         }
     }
-    node = sy * nx + sx;
 }
 
 template <class T>
@@ -241,21 +250,22 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const int64_t ushape_off = sd->ushape_off;
     const int x0 = tl.y, y0 = tl.z;
     const int plane = nx * ny;
-    const int pb = plane * SB;       // bytes per direction plane
-    const int lb = 9 * pb;           // bytes per lattice
+    constexpr int NL = CPL ? 3 : 2;     // lattices
+    constexpr int RUN = 64 * SB;        // bytes per direction vector of a run
+    constexpr int BLK = NL * 9 * RUN;   // bytes per run block
+    const int nbx = (nx + 63) >> 6;     // runs per grid row
+    const int RB = nbx * BLK;           // bytes per grid row
     const char* srcb = static_cast<const char*>(a.src) + sd->off * SB;
-    const __amdgpu_buffer_rsrc_t rF = make_rsrc(srcb, lb);
-    const __amdgpu_buffer_rsrc_t rH = make_rsrc(srcb + lb, lb);
-    const __amdgpu_buffer_rsrc_t rG = make_rsrc(srcb + (CPL ? 2 * (int64_t)lb : 0), lb);
     const int64_t step = *a.step_in;
-    // tile, its radius-2 halo and their pull sources inside the grid: no
-    // wrapping, no walls
     // tile, its radius-2 halo and their pull sources clear of the walls (or
     // of the y wrap), on a grid at least a tile and its halo wide: x wraps
     // per lane on the fast path
     const bool inner = y0 >= 3 && y0 + TY + 3 <= ny && nx >= TW + 3;
-    int so[9];
-    pull_offsets(pb, nx, SB, so);
+    const int sim_bytes = ny * RB;
+    const __amdgpu_buffer_rsrc_t rF = make_rsrc(srcb, sim_bytes);
+    const __amdgpu_buffer_rsrc_t rH = make_rsrc(srcb + 9 * RUN, sim_bytes - 9 * RUN);
+    const __amdgpu_buffer_rsrc_t rG =
+        make_rsrc(srcb + (CPL ? 18 * RUN : 0), sim_bytes - (CPL ? 18 * RUN : 0));
 
     const int tid = threadIdx.x;
     static_assert((WX & (WX - 1)) == 0, "WX must be a power of two");
@@ -276,15 +286,15 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         const int gy = y0 + iy;
         if (inner) {
             int vo, xp, xm;
-            wrap_offsets<SB>(lx, gy, nx, vo, xp, xm);
-            pull9_inner<S, T>(rF, vo, xp, xm, so, qf[j]);
-            pull9_inner<S, T>(rH, vo, xp, xm, so, qh[j]);
-            if constexpr (CPL) pull9_inner<S, T>(rG, vo, xp, xm, so, qg[j]);
+            run_offsets<SB>(lx, gy, nx, nbx, BLK, vo, xp, xm);
+            pull9_inner<S, T>(rF, vo, xp, xm, RB, qf[j]);
+            pull9_inner<S, T>(rH, vo, xp, xm, RB, qh[j]);
+            if constexpr (CPL) pull9_inner<S, T>(rG, vo, xp, xm, RB, qg[j]);
         } else {
             const int ly = WALLS ? mirror_coord(gy, ny) : wrap_coord(gy, ny);
-            pull9_edge<S, T, WALLS>(rF, pb, lx, ly, nx, ny, qf[j]);
-            pull9_edge<S, T, WALLS>(rH, pb, lx, ly, nx, ny, qh[j]);
-            if constexpr (CPL) pull9_edge<S, T, WALLS>(rG, pb, lx, ly, nx, ny, qg[j]);
+            pull9_edge<S, T, WALLS>(rF, lx, ly, nx, ny, nbx, BLK, qf[j]);
+            pull9_edge<S, T, WALLS>(rH, lx, ly, nx, ny, nbx, BLK, qh[j]);
+            if constexpr (CPL) pull9_edge<S, T, WALLS>(rG, lx, ly, nx, ny, nbx, BLK, qg[j]);
         }
     }
 #pragma unroll
@@ -332,14 +342,14 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         if (inner) {
             hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
             int vo, xp, xm;
-            wrap_offsets<SB>(hx, hy, nx, vo, xp, xm);
-            pull9_inner<S, T>(rF, vo, xp, xm, so, q);
+            run_offsets<SB>(hx, hy, nx, nbx, BLK, vo, xp, xm);
+            pull9_inner<S, T>(rF, vo, xp, xm, RB, q);
             phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
             if (r1) {
-                pull9_inner<S, T>(rH, vo, xp, xm, so, q);
+                pull9_inner<S, T>(rH, vo, xp, xm, RB, q);
                 cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
                 if constexpr (CPL) {
-                    pull9_inner<S, T>(rG, vo, xp, xm, so, q);
+                    pull9_inner<S, T>(rG, vo, xp, xm, RB, q);
                     to_dev<S, T>(q, k.inv_g);
                     pL[qi] = zeroth(q);
                 }
@@ -347,13 +357,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         } else {
             hx = wrap_coord(hx, nx);
             hy = WALLS ? mirror_coord(hy, ny) : wrap_coord(hy, ny);
-            pull9_edge<S, T, WALLS>(rF, pb, hx, hy, nx, ny, q);
+            pull9_edge<S, T, WALLS>(rF, hx, hy, nx, ny, nbx, BLK, q);
             phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
             if (r1) {
-                pull9_edge<S, T, WALLS>(rH, pb, hx, hy, nx, ny, q);
+                pull9_edge<S, T, WALLS>(rH, hx, hy, nx, ny, nbx, BLK, q);
                 cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
                 if constexpr (CPL) {
-                    pull9_edge<S, T, WALLS>(rG, pb, hx, hy, nx, ny, q);
+                    pull9_edge<S, T, WALLS>(rG, hx, hy, nx, ny, nbx, BLK, q);
                     to_dev<S, T>(q, k.inv_g);
                     pL[qi] = zeroth(q);
                 }
@@ -381,9 +391,10 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         if (sd->vel_period_T != 0.0) tf = T(cos(M_PI * (double)step / sd->vel_period_T));
     }
     char* dstb = static_cast<char*>(a.dst) + sd->off * SB;
-    const __amdgpu_buffer_rsrc_t wF = make_rsrc(dstb, lb);
-    const __amdgpu_buffer_rsrc_t wH = make_rsrc(dstb + lb, lb);
-    const __amdgpu_buffer_rsrc_t wG = make_rsrc(dstb + (CPL ? 2 * (int64_t)lb : 0), lb);
+    const __amdgpu_buffer_rsrc_t wF = make_rsrc(dstb, sim_bytes);
+    const __amdgpu_buffer_rsrc_t wH = make_rsrc(dstb + 9 * RUN, sim_bytes - 9 * RUN);
+    const __amdgpu_buffer_rsrc_t wG =
+        make_rsrc(dstb + (CPL ? 18 * RUN : 0), sim_bytes - (CPL ? 18 * RUN : 0));
     const bool urho = sd->uniform_rho, unu = sd->uniform_nu;
     const uint32_t step_key = fmix32((uint32_t)step * 0x9E3779B9u + 0x2504u);
     int fault = 0;
@@ -488,7 +499,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             }
             if (valid) {
                 const int own = gy * nx + gx;
-                const int vo = own * SB;
+                const int vo = (gy * nbx + (gx >> 6)) * BLK + (gx & 63) * SB;
                 uint32_t rs = 0;
                 if constexpr (Store<S>::scaled) rs = node_step_seed(node_base + (uint32_t)own, step_key);
                 // moving wall: the slots of directions pointing into the wall
@@ -503,13 +514,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 }
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    const int so_q = q * pb;
-                    Buf<S>::template store<CP>(wF, vo, so_q, qf[j][q], rs + weyl(3 * q));
-                    Buf<S>::template store<CP>(wH, vo, so_q, qh[j][q], rs + weyl(3 * q + 1));
+                    const int off = vo + q * RUN;
+                    Buf<S>::template store<CP>(wF, off, 0, qf[j][q], rs + weyl(3 * q));
+                    Buf<S>::template store<CP>(wH, off, 0, qh[j][q], rs + weyl(3 * q + 1));
                     if constexpr (CPL) {
                         T v = qg[j][q];
                         if (WALLS && wdir != 0 && EYa(q) == wdir) v += wcorr * T(EXa(q));
-                        Buf<S>::template store<CP>(wG, vo, so_q, v, rs + weyl(3 * q + 2));
+                        Buf<S>::template store<CP>(wG, off, 0, v, rs + weyl(3 * q + 2));
                     }
                 }
             }
@@ -585,13 +596,13 @@ __global__ __launch_bounds__(WG) void k_init(const InitArgs a) {
         flow_post_raw(t, ux, uy, sd->P_ref, r);
         pinv_encode(r, sd->scale_g, 0.0, sg);
     }
+    const int nl = cpl ? 3 : 2, nbx = (nx + 63) >> 6;
     for (int q = 0; q < 9; ++q) {
-        int pq, node;
-        pull_slot(x, y, q, nx, ny, a.walls != 0, pq, node);
-        // 64-bit: 26 planes of the largest FP16 lattice exceed 2^31 elements
-        pop[(int64_t)pq * plane + node] = S(phin + sf[q]);
-        pop[(int64_t)(9 + pq) * plane + node] = S(chn + sh[q]);
-        if (cpl) pop[(int64_t)(18 + pq) * plane + node] = S(sg[q]);
+        int pq, sx, sy;
+        pull_slot(x, y, q, nx, ny, a.walls != 0, pq, sx, sy);
+        pop[pelem(0, pq, sx, sy, nbx, nl)] = S(phin + sf[q]);
+        pop[pelem(1, pq, sx, sy, nbx, nl)] = S(chn + sh[q]);
+        if (cpl) pop[pelem(2, pq, sx, sy, nbx, nl)] = S(sg[q]);
     }
     if (a.flow == FLOW_PRESCRIBED && a.ushape) {
         T* us = static_cast<T*>(a.ushape);
@@ -614,9 +625,10 @@ __global__ __launch_bounds__(WG) void k_decode(const void* pop, const SimDev* sd
     const int lat = (int)(i / (9 * (int64_t)plane));
     const int q = (int)((i / plane) % 9);
     const int n = (int)(i % plane);
-    int pq, node;
-    pull_slot(n % nx, n / nx, q, nx, ny, walls != 0, pq, node);
-    const double s = double(static_cast<const S*>(pop)[((int64_t)lat * 9 + pq) * plane + node]);
+    int pq, sx, sy;
+    pull_slot(n % nx, n / nx, q, nx, ny, walls != 0, pq, sx, sy);
+    const double s =
+        double(static_cast<const S*>(pop)[pelem(lat, pq, sx, sy, (nx + 63) >> 6, nlat)]);
     const double w = wgt<double>(q);
     const double scale = lat == 0 ? sd->scale_f : (lat == 1 ? sd->scale_h : sd->scale_g);
     const double qref = lat == 0 ? sd->qref_f : (lat == 1 ? 0.0 : sd->P_ref);
@@ -633,12 +645,12 @@ __global__ __launch_bounds__(WG) void k_encode(void* pop, const SimDev* sd, int 
     const int lat = (int)(i / (9 * (int64_t)plane));
     const int q = (int)((i / plane) % 9);
     const int n = (int)(i % plane);
-    int pq, node;
-    pull_slot(n % nx, n / nx, q, nx, ny, walls != 0, pq, node);
+    int pq, sx, sy;
+    pull_slot(n % nx, n / nx, q, nx, ny, walls != 0, pq, sx, sy);
     const double scale = lat == 0 ? sd->scale_f : (lat == 1 ? sd->scale_h : sd->scale_g);
     const double qref = lat == 0 ? sd->qref_f : (lat == 1 ? 0.0 : sd->P_ref);
     const double s = (in[i] * inv_wgt<double>(q) - qref) * scale;
-    static_cast<S*>(pop)[((int64_t)lat * 9 + pq) * plane + node] = S(s);
+    static_cast<S*>(pop)[pelem(lat, pq, sx, sy, (nx + 63) >> 6, nlat)] = S(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,22 +666,22 @@ __global__ __launch_bounds__(WG) void k_encode(void* pop, const SimDev* sd, int 
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const SimDev* sims,
-                                                       int first, int max_ny, int row_base,
-                                                       double* rows) {
+                                                       int nl, int first, int max_ny,
+                                                       int row_base, double* rows) {
     const SimDev* sd = sims + first + (int)(blockIdx.x / max_ny);
-    const int nx = sd->nx, ny = sd->ny, plane = nx * ny;
+    const int nx = sd->nx, ny = sd->ny;
     const int y = (int)(blockIdx.x % max_ny);
     if (y >= ny) return;
     const S* p = static_cast<const S*>(pop) + sd->off;
     const double inv_f = 1.0 / sd->scale_f, inv_h = 1.0 / sd->scale_h, qref = sd->qref_f;
+    const int nbx = (nx + 63) >> 6;
     double sf = 0.0, sh = 0.0;
     for (int x = threadIdx.x; x < nx; x += WG) {
-        const int i = y * nx + x;
         double vf = 0.0, vh = 0.0;
         for (int q = 0; q < 9; ++q) {
             const double w = wgt<double>(q);
-            vf += w * (double(p[(int64_t)q * plane + i]) * inv_f + qref);
-            vh += w * (double(p[(int64_t)(9 + q) * plane + i]) * inv_h);
+            vf += w * (double(p[pelem(0, q, x, y, nbx, nl)]) * inv_f + qref);
+            vh += w * (double(p[pelem(1, q, x, y, nbx, nl)]) * inv_h);
         }
         sf += vf;
         sh += vh;

@@ -135,6 +135,14 @@ def test_validation_before_device(lib):
     assert _create(lib, [dict(cpl, omega_zeta=2.5)])[0] == cmlb.EUNSTABLE
     assert _create(lib, [dict(cpl, nu_a=-0.2)])[0] in (cmlb.EINVAL, cmlb.EUNSTABLE)
     assert _create(lib, [dict(good, M_phi=-0.1)])[0] == cmlb.EINVAL
+    # a simulation's population block (rows padded to runs of 64 nodes)
+    # must fit 2^31 bytes: 27 x 4 B x 4096 x 4800 fits, 4096 x 4864 does not;
+    # the padding counts (4033 columns take 64 runs)
+    big = dict(cpl, nx=4096, ny=4864)
+    assert _create(lib, [big], prec=1)[0] == cmlb.EINVAL
+    assert _create(lib, [dict(big, nx=4033)], prec=1)[0] == cmlb.EINVAL
+    assert _create(lib, [dict(big, nx=4096, ny=2432)], prec=0)[0] == cmlb.EINVAL
+    assert _create(lib, [dict(big, nx=8192, ny=4864)], prec=2)[0] == cmlb.EINVAL
     # null output handle
     arr = (cmlb.SimParams * 1)(cmlb.make_params(good))
     assert lib.cmlb_create(arr, 1, 0, None, None) == cmlb.EINVAL

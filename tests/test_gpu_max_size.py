@@ -1,6 +1,8 @@
-"""Lattices above 1 GiB, up to the 2 GiB a lattice may take (one 32-bit
-buffer range per lattice): the flow lattice g starts 2 lattices into a
-simulation's block, which no longer fits a 32-bit byte offset.
+"""Simulations at the size limit.  In 2D a simulation's whole population
+block (three lattices in runs of 64 nodes) must fit one 32-bit buffer range:
+the largest FP32 coupled drop tested holds 2.12 GB.  In 3D a lattice must fit
+one 32-bit range, and the flow lattice g starts 2 lattices into a
+simulation's block, beyond a 32-bit byte offset.
 
 One step of a coupled shear drop at that size is checked window by window
 against the FP64 oracle: a node's next pre-collision populations depend on
@@ -30,11 +32,13 @@ def _window3(a, x0, y0, z0):
     return np.ascontiguousarray(a[:, z0:z0 + WIN, y0:y0 + WIN, x0:x0 + WIN])
 
 
-def test_2d_lattice_above_1gib_fp32(oracle_mod, gpu_lib):
-    """8192 x 4864 coupled shear drop in FP32: 1.43 GB per lattice."""
+def test_2d_simulation_at_the_2gib_limit_fp32(oracle_mod, gpu_lib):
+    """4096 x 4800 coupled shear drop in FP32: a 2.12 GB population block,
+    within 1.2% of the 2^31-byte limit (one more row of 4096 nodes fits, the
+    next size up is rejected)."""
     from paper_2504_09024_amd import cmlb
-    nx, ny = 8192, 4864
-    assert 9 * nx * ny * 4 > 2 ** 30
+    nx, ny = 4096, 4800
+    assert 27 * nx * ny * 4 < 2 ** 31 <= 27 * nx * (ny + 64) * 4
     p, fl = W.shear_drop(nx=nx, ny=ny, R=64.0, Re=1.0)
     ctx = cmlb.Context(p, "fp32")
     ctx.init_fields(0, fl["phi"], fl["c"], fl["ux"], fl["uy"])
