@@ -277,6 +277,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const int lx = inner ? (gx < nx ? gx : gx - nx) : wrap_coord(gx, nx);
 
     // ---------------- phase 1: own nodes -----------------------------------
+    // FP32 storage: the wave issues its own pulls at raised priority, so a
+    // wave entering the step gets its loads out ahead of the arithmetic of
+    // the other waves on its SIMD (64-drop batch: +4% in FP32; the same in
+    // FP16 or FP64 costs 8-10%, there the arithmetic is the scarcer
+    // resource, so they keep the default priority).
+    constexpr bool LOAD_PRIO = std::is_same_v<S, float>;
+    if constexpr (LOAD_PRIO) __builtin_amdgcn_s_setprio(2);
     T qf[NPT][9], qh[NPT][9], qg[CPL ? NPT : 1][9];
     T phv[NPT], cv[NPT], phn[NPT], chn[NPT], jfx[NPT], jfy[NPT], jhx[NPT], jhy[NPT];
     Raw6<T> mg[CPL ? NPT : 1];
@@ -297,6 +304,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             if constexpr (CPL) pull9_edge<S, T, WALLS>(rG, lx, ly, nx, ny, nbx, BLK, qg[j]);
         }
     }
+    if constexpr (LOAD_PRIO) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
         const int iy = wave * NPT + j;
@@ -318,7 +326,14 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         }
     }
     // ---------------- phase 1b: halo ring ----------------------------------
-    for (int i = tid; i < RING; i += NT) {
+    // a compile-time trip count: with a runtime loop the ring's values and
+    // the own nodes' populations outgrow 128 VGPRs in 128-wide tiles (two
+    // ring nodes per thread) and spill
+    constexpr int RITER = (RING + NT - 1) / NT;
+#pragma unroll
+    for (int it = 0; it < RITER; ++it) {
+        const int i = tid + it * NT;
+        if (i >= RING) break;
         int ry, rx;
         if (i < 2 * PW) {
             ry = i / PW;
