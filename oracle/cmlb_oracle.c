@@ -472,8 +472,10 @@ static void node_macros(const o_params* p, const double w[9], const fields_t* F,
         double weight, ks;
         const double phio = 0.5 * dphi;
         if (p->force_abs_grad) {
-            weight = s->gmag;
-            ks = 1.0 / dphi;
+            /* plant 19: |grad phi|^2 kept in the |grad phi| reading;
+             * plant 20: its normalisation 1/(phi_a - phi_b) dropped */
+            weight = PLANT(19) ? s->gmag * s->gmag : s->gmag;
+            ks = PLANT(20) ? 1.0 : 1.0 / dphi;
         } else {
             weight = s->gmag * s->gmag;
             /* plant 1: F_s without the normalisation k_s */

@@ -186,6 +186,32 @@ def test_laplace_law(oracle_mod, rho_a):
     assert 0.85 < ratio < 1.02, ratio
 
 
+def test_laplace_law_abs_grad_reading(oracle_mod):
+    """The alternative reading of Eq. Fs kept as an oracle option: the
+    surface delta |grad phi| (which integrates to phi_a - phi_b across the
+    interface) in place of |grad phi|^2, normalised by 1/(phi_a - phi_b).
+    Laplace's law then holds with the same sigma0: on a drop with
+    phi_a = 2 (so that a dropped 1/(phi_a - phi_b) or a squared weight shows)
+    the pressure jump is 1.03 sigma0/R, where the default reading gives 0.94
+    (the nine-point gradient over-resolves |grad phi| slightly and
+    under-resolves |grad phi|^2 by 7% at W = 4)."""
+    n, R, sig = 48, 12.0, 0.01
+    p = W.params(nx=n, ny=n, flow="coupled", sigma0=sig, beta=0.0, M_phi=0.05, D_s=0.01,
+                 omega_zeta=0.8, phi_a=2.0, phi_b=0.0)
+    phi, c = W.drop_fields(n, n, n / 2, n / 2, R, 4.0, None)
+    op = oracle_mod.make_params(**p)
+    op.force_abs_grad = 1
+    s = oracle_mod.OracleSim(op, 2.0 * phi, c, None, None, np.full_like(phi, 1.0 / 3.0))
+    s.run(1500)
+    vals = []
+    for _ in range(50):
+        s.run(10)
+        P = s.fields()["P"]
+        vals.append(P[n // 2 - 2:n // 2 + 2, n // 2 - 2:n // 2 + 2].mean() - P[:3, :3].mean())
+    ratio = np.mean(vals) / (sig / R)
+    assert 0.98 < ratio < 1.08, ratio
+
+
 def test_wall_ghost_normal_mirrors(oracle_mod):
     """Ghost rows mirror phi about the wall plane, and the normal there is
     computed from those ghost values.  A drop centred on the lower wall plane

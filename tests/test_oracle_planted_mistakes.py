@@ -40,6 +40,8 @@ PLANTS = {
     16: "test_translating_density_layer",           # F_p from P^ instead of psi^
     17: "test_sound_wave_damping",                  # trace relaxed at the shear rate
     18: "test_layered_couette_viscosity_ratio",     # the two viscosities interchanged
+    19: "test_laplace_law_abs_grad_reading",        # |grad phi|^2 kept in the |grad phi| reading
+    20: "test_laplace_law_abs_grad_reading",        # its 1/(phi_a - phi_b) dropped
     21: "test_z_uniform_field_reduces_to_the_2d_oracle",  # 3D gradient without 1/cs2
     22: "test_axis_inverse_matches_dense_solve",    # 3D inverse, moving pair swapped
     23: "test_sound_wave_damping_3d",               # 3D trace at the shear rate
