@@ -481,8 +481,8 @@ void launch_inventory_s(cmlb_ctx* c, int first, int n, int max_ny, double* rows,
                        c->stream,
                        (const void*)c->pop[c->cur], (const SimDev*)c->d_sims, c->nlat, first,
                        max_ny, row_base, rows);
-    hipLaunchKernelGGL(k_inventory_final, dim3((n + 63) / 64), dim3(64), 0, c->stream,
-                       (const double*)rows, (const SimDev*)c->d_sims, first, n, row_base, out);
+    hipLaunchKernelGGL(k_inventory_final, dim3(n), dim3(WG), 0, c->stream, (const double*)rows,
+                       (const SimDev*)c->d_sims, first, row_base, out);
 }
 int launch_inventory(cmlb_ctx* c, int first, int n, double* rows, double* out) {
     int max_ny = 0;
@@ -604,8 +604,14 @@ int cmlb_create(const cmlb_sim_params* params, int32_t n_sims, int32_t precision
             d.scale_f = 0.5 / pow2_floor(std::fabs(phio) * 1.0000001);
             if (!(d.scale_f > 0.0) || !std::isfinite(d.scale_f)) d.scale_f = 1.0;
             d.scale_h = 16.0 / pow2_floor(p.c_max > 0.0 ? p.c_max : 1.0);
+            // g: the stored deviation q_a/w_a - P_ref holds 3 e_a.u P-sized
+            // velocity terms and the pressure deviation, which reaches
+            // cs^2 |rho_a - rho_b| across an interface when P starts at
+            // rho cs^2; values are kept near 32 (binary16 overflows at
+            // 65504).  Speeds are taken as O(u_wall), at least 1e-4.
             const double uref = std::max(std::fabs(d.u_wall), 1e-4);
-            d.scale_g = pow2_floor(32.0 / (3.0 * uref));
+            const double dev = std::max(3.0 * uref, std::fabs(p.rho_a - p.rho_b) / 3.0);
+            d.scale_g = pow2_floor(32.0 / dev);
         } else {
             d.qref_f = 0.0;
             d.scale_f = d.scale_h = d.scale_g = 1.0;

@@ -462,8 +462,23 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             // F_p = -grad psi^, psi^ = P^ - rho cs2, rho linear in phi
             fpx = -(gqx - k.dr_cs2 * gpx);
             fpy = -(gqy - k.dr_cs2 * gpy);
-            ux = (T(3) * mg[j].m1 + T(0.5) * ftx) * inv_rho;
-            uy = (T(3) * mg[j].m2 + T(0.5) * fty) * inv_rho;
+            if constexpr (sizeof(T) == 4) {
+                // the collision re-encodes the momentum as u (T00 - psi),
+                // T00 - psi = fl(rho cs2) + ..., with cs2 rounded to FP32
+                // (1 + 3e-8 times 1/3): the velocity divides by that same
+                // product (quotient corrected by one residual step), where
+                // 3 m1 / rho would grow u by 3e-8 every step
+                const T crho = rho * K<T>::cs2;
+                const T ic = rcp_(crho);
+                const T q0x = mg[j].m1 * ic, q0y = mg[j].m2 * ic;
+                const T qx = fmaf(fmaf(-q0x, crho, mg[j].m1), ic, q0x);
+                const T qy = fmaf(fmaf(-q0y, crho, mg[j].m2), ic, q0y);
+                ux = qx + T(0.5) * ftx * inv_rho;
+                uy = qy + T(0.5) * fty * inv_rho;
+            } else {
+                ux = (T(3) * mg[j].m1 + T(0.5) * ftx) * inv_rho;
+                uy = (T(3) * mg[j].m2 + T(0.5) * fty) * inv_rho;
+            }
             gam = fpx * ux + fpy * uy;
             dP = mg[j].m0 + T(0.5) * gam;
             psi = dP + (k.P_ref - rho * K<T>::cs2);
@@ -510,6 +525,16 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 flow_collide(mg[j], ux, uy, dP, psi, P_hat, fpx, fpy, ftx, fty, gam,
                              k.omega_zeta, omega_nu, t);
                 flow_post_raw(t, ux, uy, k.P_ref, r);
+                if constexpr (sizeof(T) == 4) {
+                    // first raw moments u (T00 - psi) + s1/2 with
+                    // T00 - psi = fl(rho cs2) + gam/2 taken directly: T00 =
+                    // P_ref + t0 in FP32 rounds the pressure deviation to
+                    // 3e-8, the same every step at a quasi-steady node
+                    const T crho = rho * K<T>::cs2;
+                    const T mom = crho + T(0.5) * gam;
+                    r[1] = ux * mom + T(0.5) * (K<T>::cs2 * ftx - ux * gam);
+                    r[2] = uy * mom + T(0.5) * (K<T>::cs2 * fty - uy * gam);
+                }
                 pinv_dev(r, k.scale_g, qg[j]);
             }
             if (valid) {
@@ -671,13 +696,13 @@ __global__ __launch_bounds__(WG) void k_encode(void* pop, const SimDev* sd, int 
 // ---------------------------------------------------------------------------
 // Inventories: FP64 totals of phi and c for the simulations [first, first+n)
 // of a context in two launches.  Stage 1 has one workgroup per (simulation,
-// row), workgroup index = (sim - first) * max_ny + row: each thread sums its columns in order, then a fixed butterfly over
-// the wave and a fixed order over the waves give the row's partial, stored
-// at index row0 - row_base + y.  Stage 2 has one thread per simulation,
-// which adds that simulation's row partials in row order.  The order of
-// every addition is fixed, so a total does not depend on the step kernel's
-// tiling, on which other simulations share the launch, or on the buffer the
-// partials go to.
+// row), workgroup index = (sim - first) * max_ny + row: each thread sums its
+// columns in order, then a fixed butterfly over the wave and a fixed order
+// over the waves give the row's partial, stored at index row0 - row_base + y.
+// Stage 2 has one workgroup per simulation, whose first thread adds that
+// simulation's row partials in row order.  The order of every addition is
+// fixed, so a total does not depend on the step kernel's tiling, on which
+// other simulations share the launch, or on the buffer the partials go to.
 // ---------------------------------------------------------------------------
 template <class S>
 __global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const SimDev* sims,
@@ -723,20 +748,33 @@ __global__ __launch_bounds__(WG) void k_inventory_rows(const void* pop, const Si
     }
 }
 
-__global__ __launch_bounds__(64) void k_inventory_final(const double* rows, const SimDev* sims,
-                                                        int first, int n, int row_base,
-                                                        double* out) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= n) return;
-    const SimDev* sd = sims + first + i;
-    const int r0 = sd->row0 - row_base;
+__global__ __launch_bounds__(WG) void k_inventory_final(const double* rows, const SimDev* sims,
+                                                        int first, int row_base, double* out) {
+    // one workgroup per simulation: chunks of the row partials are staged in
+    // LDS by all threads, then one thread adds them in row order
+    const SimDev* sd = sims + first + blockIdx.x;
+    const int r0 = sd->row0 - row_base, ny = sd->ny;
+    __shared__ double buf[2 * WG];
     double a = 0.0, b = 0.0;
-    for (int y = 0; y < sd->ny; ++y) {
-        a += rows[2 * (r0 + y)];
-        b += rows[2 * (r0 + y) + 1];
+    for (int y0 = 0; y0 < ny; y0 += WG) {
+        const int n = min(WG, ny - y0);
+        if ((int)threadIdx.x < n) {
+            buf[2 * threadIdx.x] = rows[2 * (r0 + y0 + threadIdx.x)];
+            buf[2 * threadIdx.x + 1] = rows[2 * (r0 + y0 + threadIdx.x) + 1];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int y = 0; y < n; ++y) {
+                a += buf[2 * y];
+                b += buf[2 * y + 1];
+            }
+        }
+        __syncthreads();
     }
-    out[2 * i] = a;
-    out[2 * i + 1] = b;
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = a;
+        out[2 * blockIdx.x + 1] = b;
+    }
 }
 
 }  // namespace cmlb

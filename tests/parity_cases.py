@@ -35,6 +35,16 @@ def _shear_ratio():
     return p, dict(fl, P=np.full_like(fl["phi"], p["rho_b"] / 3.0))
 
 
+def _density_ratio4():
+    """A drop four times as dense as its surroundings in a periodic box,
+    surface tension only, started from a uniform pressure (near rest)."""
+    n = 64
+    p = W.params(nx=n, ny=n, flow="coupled", bc_y="periodic", sigma0=1e-3, beta=0.2,
+                 M_phi=0.05, D_s=0.02, rho_a=4.0, rho_b=1.0, nu_a=0.1, nu_b=0.1)
+    phi, c = W.drop_fields(n, n, 31.7, 32.4, 12.0, 4.0, 0.3)
+    return p, dict(phi=phi, c=c, P=np.full_like(phi, 1.0 / 3.0))
+
+
 CASES = {
     # static drop of Sec. 4.1 at the 128x128 scale, all 2000 steps
     "c1_static_drop": (lambda: W.static_drop(), 2000),
@@ -66,6 +76,7 @@ CASES = {
     # rounding floor with it) and 5 x 6 with walls
     "tiny_periodic": (lambda: _tiny(4, 4, "periodic"), 5),
     "tiny_walls": (lambda: _tiny(5, 6, "walls"), 50),
+    "density_ratio4_fp16": (_density_ratio4, 200),
 }
 
 # cases compared against the FP64 bar (1e-12) and cheap enough for the CPU
@@ -77,4 +88,8 @@ FP64_CONDITIONING = ["ragged_periodic", "vortex", "shear_drop", "shear_ratio", "
 # a one-time relative perturbation of phi by one FP16 rounding (2.4e-4)
 # must not grow over the run
 FP16_CONDITIONING = [("c1_static_drop", 500), ("vortex", 400), ("shear_drop", 200),
-                     ("shear_ratio", 200)]
+                     ("shear_ratio", 200), ("density_ratio4_fp16", 200)]
+# fields an FP16 case is compared on (default phi, c and u): the velocity of
+# the dense drop at rest is its spurious current, whose relative error the
+# problem amplifies, so that case is held to the bar on phi and c
+FP16_FIELDS = {"density_ratio4_fp16": ("phi", "c")}
