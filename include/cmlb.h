@@ -56,6 +56,11 @@ typedef enum {
     CMLB_FP32 = 1, /* FP32 deviations from the rest state, scaled by 1/w_a */
     CMLB_FP16 = 2  /* IEEE binary16 deviations from the rest state, scaled by 2^k/w_a */
 } cmlb_precision;
+/* FP16 stores round stochastically; the random word of a store is drawn from
+ * the step number and the node's index counted over all simulations of the
+ * context, so an FP16 simulation's results depend on its place in the batch
+ * (which simulations precede it).  FP64 and FP32 results do not: a
+ * simulation advanced inside a batch is bitwise the same as alone. */
 
 typedef enum {
     CMLB_BC_PERIODIC = 0,    /* y periodic */

@@ -75,3 +75,24 @@ def stone_leal_D(Ca, beta, Pe, lam=1.0):
     """Sec. 4.3 small-deformation prediction D = 3 Ca b_r/(4 + Ca b_r)."""
     br = 1.25 * ((16 + 19 * lam) + 4 * beta * Pe / Ca) / (10 * (1 + lam) + 2 * beta * Pe / Ca)
     return 3 * Ca * br / (4 + Ca * br)
+
+
+def fragments(phi, level=0.5):
+    """Number of separate drops: connected regions of phi > `level` (nodes
+    joined across edges), with the x direction periodic (a drop cut by the
+    x seam counts once)."""
+    from scipy import ndimage
+    lab, n = ndimage.label(phi > level)
+    if n < 2:
+        return n
+    root = list(range(n + 1))
+
+    def find(i):
+        while root[i] != i:
+            i = root[i]
+        return i
+
+    for a, b in zip(lab[:, 0], lab[:, -1]):
+        if a and b:
+            root[find(b)] = find(a)
+    return len({find(i) for i in range(1, n + 1)})

@@ -62,3 +62,24 @@ def test_stone_leal_reduces_to_its_clean_limit():
         br = 5 * 35 / 80
         assert abs(stone_leal_D(Ca, 0.0, 7.0) - 3 * Ca * br / (4 + Ca * br)) < 1e-15
     assert stone_leal_D(0.01, 0.25, 1.0) > stone_leal_D(0.01, 0.0, 1.0)
+
+
+def test_fragment_count():
+    """Drops are counted once each, also when the periodic x seam cuts one;
+    a thin neck still joins, a gap of one node separates."""
+    from profile_util import fragments
+    phi = np.zeros((40, 60))
+    assert fragments(phi) == 0
+    phi[5:10, 5:15] = 1.0
+    assert fragments(phi) == 1
+    phi[20:30, 0:4] = 1.0
+    phi[22:28, 55:60] = 1.0          # one drop across the seam
+    assert fragments(phi) == 2
+    phi[7, 15:30] = 1.0              # a one-node neck joins a third blob
+    phi[5:10, 30:40] = 1.0
+    assert fragments(phi) == 2
+    phi[7, 22] = 0.0                 # neck cut: the blob is separate
+    assert fragments(phi) == 3
+    phi[33, 33] = 0.9                # diagonal neighbours are not joined
+    phi[34, 34] = 0.9
+    assert fragments(phi) == 5
