@@ -1,7 +1,8 @@
 // Device helpers shared by the 2D (D2Q9) and 3D (D3Q27) step kernels:
 // population storage through buffer descriptors in FP64, FP32 or binary16
 // (stochastic rounding), the counter-based random words of that rounding,
-// fast FP32 reciprocal / square root / logarithm, and coordinate folding.
+// fast FP32 reciprocal / square root / logarithm, unbiased FP32 division by
+// small constants, and coordinate folding.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -146,6 +147,20 @@ __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float log_(float x) { return __logf(x); }
 __device__ __forceinline__ double log_(double x) { return log(x); }
+
+// x / D for a small integer D.  FP32 has no exact 1/9 or 1/36 (both round
+// 7.45e-9 high): a product with the rounded reciprocal carries that bias in
+// every result, and a scheme that divides by the lattice weights each step
+// then gains or loses the divided quantity by 7.45e-9 per step.  One FMA
+// residual step turns the product into the correctly rounded quotient
+// (Markstein's correction), whose errors have no sign preference.
+template <int D>
+__device__ __forceinline__ float div_const(float x) {
+    constexpr float r = 1.0f / D;
+    const float q0 = x * r;
+    const float e = __builtin_fmaf(-q0, float(D), x);
+    return __builtin_fmaf(e, r, q0);
+}
 
 // Coordinate folding: periodic wrap, or mirror about the wall planes
 // y = -1/2 and y = n - 1/2 (ghost row -1-k carries row k).

@@ -50,16 +50,16 @@ struct StepArgs {
 // Moments of stored scalar-lattice values in storage units.  No FP
 // contraction: a node's zeroth moment must carry the same bits in every code
 // path that computes it (tile interior and neighbouring tiles' halos).
-template <class T>
+template <class S, class T>
 __device__ __forceinline__ void scalar_moments_nc(const T v[9], T& m0, T& m1, T& m2) {
 #pragma clang fp contract(off)
-    scalar_moments(v, m0, m1, m2);
+    scalar_moments<T, std::is_same_v<S, float>>(v, m0, m1, m2);
 }
-template <class T>
+template <class S, class T>
 __device__ __forceinline__ T scalar_zeroth_nc(const T v[9]) {
 #pragma clang fp contract(off)
     T m0, m1, m2;
-    scalar_moments(v, m0, m1, m2);
+    scalar_moments<T, std::is_same_v<S, float>>(v, m0, m1, m2);
     return m0;
 }
 template <class T>
@@ -153,12 +153,20 @@ __device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int lx, int
     }
 }
 
-// stored g values -> deviations d_a = w_a s_a / scale
+// stored g values -> deviations d_a = w_a s_a / scale.  FP32 storage (scale
+// 1): w_a s_a as (9 w_a) s_a / 9, 9 w_a in {4, 1, 1/4} exact, with a
+// correctly rounded division, so the moments carry no common weight bias.
 template <class S, class T>
 __device__ __forceinline__ void to_dev(T v[9], T inv) {
 #pragma clang fp contract(off)
 #pragma unroll
-    for (int a = 0; a < 9; ++a) v[a] = Store<S>::scaled ? wgt<T>(a) * (v[a] * inv) : wgt<T>(a) * v[a];
+    for (int a = 0; a < 9; ++a) {
+        if constexpr (std::is_same_v<S, float>) {
+            v[a] = div_const<9>((a == 0 ? T(4) : (a < 5 ? T(1) : T(0.25))) * v[a]);
+        } else {
+            v[a] = Store<S>::scaled ? wgt<T>(a) * (v[a] * inv) : wgt<T>(a) * v[a];
+        }
+    }
 }
 
 // Slot from which node (x, y) pulls direction a: (direction plane, source
@@ -308,8 +316,8 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
         const int iy = wave * NPT + j;
-        scalar_moments_nc(qf[j], phn[j], jfx[j], jfy[j]);
-        scalar_moments_nc(qh[j], chn[j], jhx[j], jhy[j]);
+        scalar_moments_nc<S>(qf[j], phn[j], jfx[j], jfy[j]);
+        scalar_moments_nc<S>(qh[j], chn[j], jhx[j], jhy[j]);
         // true zeroth and first moments
         phv[j] = phn[j] * k.inv_f + k.qref_f;
         cv[j] = chn[j] * k.inv_h;
@@ -359,10 +367,10 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             int vo, xp, xm;
             run_offsets<SB>(hx, hy, nx, nbx, BLK, vo, xp, xm);
             pull9_inner<S, T>(rF, vo, xp, xm, RB, q);
-            phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
+            phiL[ry * PW + rx] = scalar_zeroth_nc<S>(q) * k.inv_f + k.qref_f;
             if (r1) {
                 pull9_inner<S, T>(rH, vo, xp, xm, RB, q);
-                cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
+                cL[qi] = scalar_zeroth_nc<S>(q) * k.inv_h;
                 if constexpr (CPL) {
                     pull9_inner<S, T>(rG, vo, xp, xm, RB, q);
                     to_dev<S, T>(q, k.inv_g);
@@ -373,10 +381,10 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             hx = wrap_coord(hx, nx);
             hy = WALLS ? mirror_coord(hy, ny) : wrap_coord(hy, ny);
             pull9_edge<S, T, WALLS>(rF, hx, hy, nx, ny, nbx, BLK, q);
-            phiL[ry * PW + rx] = scalar_zeroth_nc(q) * k.inv_f + k.qref_f;
+            phiL[ry * PW + rx] = scalar_zeroth_nc<S>(q) * k.inv_f + k.qref_f;
             if (r1) {
                 pull9_edge<S, T, WALLS>(rH, hx, hy, nx, ny, nbx, BLK, q);
-                cL[qi] = scalar_zeroth_nc(q) * k.inv_h;
+                cL[qi] = scalar_zeroth_nc<S>(q) * k.inv_h;
                 if constexpr (CPL) {
                     pull9_edge<S, T, WALLS>(rG, hx, hy, nx, ny, nbx, BLK, q);
                     to_dev<S, T>(q, k.inv_g);
@@ -525,7 +533,26 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 flow_collide(mg[j], ux, uy, dP, psi, P_hat, fpx, fpy, ftx, fty, gam,
                              k.omega_zeta, omega_nu, t);
                 flow_post_raw(t, ux, uy, k.P_ref, r);
-                if constexpr (sizeof(T) == 4) {
+                if constexpr (std::is_same_v<S, float>) {
+                    // FP32 storage.  The collision changes the momentum by
+                    // exactly cs2 F (u (rho cs2 + gam/2) + (cs2 F - u gam)/2
+                    // with rho cs2 u = m1 + cs2 F/2): taken as that sum, no
+                    // rounding of u enters it.  The third-order moments carry
+                    // the rest value u rho_b/9 (kappa_xx of the rest state
+                    // times u); formed as u (t + cs2 P_ref) it would take the
+                    // 7.45e-9 bias of the rounded 1/9 every step, and these
+                    // two moments decide the momentum a moving wall hands to
+                    // the fluid (a steady slip of 1e-5 of the wall speed in
+                    // the 1024 x 512 shear drop).
+                    const T uxuy = ux * uy, ux2 = ux * ux, uy2 = uy * uy;
+                    const T T00 = t[0] + k.P_ref;
+                    r[1] = mg[j].m1 + K<T>::cs2 * ftx;
+                    r[2] = mg[j].m2 + K<T>::cs2 * fty;
+                    r[6] = ux2 * uy * T00 + T(2) * uxuy * t[1] + ux2 * t[2] + uy * t[3] +
+                           div_const<9>(uy * k.rho_b) + T(2) * ux * t[5] + t[6];
+                    r[7] = ux * uy2 * T00 + uy2 * t[1] + T(2) * uxuy * t[2] + ux * t[4] +
+                           div_const<9>(ux * k.rho_b) + T(2) * uy * t[5] + t[7];
+                } else if constexpr (sizeof(T) == 4) {
                     // first raw moments u (T00 - psi) + s1/2 with
                     // T00 - psi = fl(rho cs2) + gam/2 taken directly: T00 =
                     // P_ref + t0 in FP32 rounds the pressure deviation to

@@ -152,14 +152,23 @@ __device__ __forceinline__ void raw_moments3(const T d[9], T& m0, T& m1, T& m2) 
 // pairwise differences.  Both are exact when all v_a are equal, so a node at
 // rest in a bulk phase reproduces its own bits every step (no drift of the
 // bulk values through rounding).
-template <class T>
+// EXACT (FP32 storage): the weights enter as one correctly rounded division
+// by 36 of an integer-weighted sum rather than as products with the rounded
+// 1/9 and 1/36, whose common bias would scale the moments by 1 + 7.45e-9.
+template <class T, bool EXACT = false>
 __device__ __forceinline__ void scalar_moments(const T v[9], T& m0, T& m1, T& m2) {
     const T v4 = T(4) * v[0];
     const T A = (v[1] + v[2]) + (v[3] + v[4]);
     const T B = (v[5] + v[6]) + (v[7] + v[8]);
-    m0 = v[0] + (T(4) * (A - v4) + (B - v4)) * T(1.0 / 36.0);
-    m1 = (v[1] - v[3]) * T(1.0 / 9.0) + ((v[5] - v[6]) + (v[8] - v[7])) * T(1.0 / 36.0);
-    m2 = (v[2] - v[4]) * T(1.0 / 9.0) + ((v[5] + v[6]) - (v[7] + v[8])) * T(1.0 / 36.0);
+    if constexpr (EXACT) {
+        m0 = v[0] + div_const<36>(T(4) * (A - v4) + (B - v4));
+        m1 = div_const<36>(T(4) * (v[1] - v[3]) + ((v[5] - v[6]) + (v[8] - v[7])));
+        m2 = div_const<36>(T(4) * (v[2] - v[4]) + ((v[5] + v[6]) - (v[7] + v[8])));
+    } else {
+        m0 = v[0] + (T(4) * (A - v4) + (B - v4)) * T(1.0 / 36.0);
+        m1 = (v[1] - v[3]) * T(1.0 / 9.0) + ((v[5] - v[6]) + (v[8] - v[7])) * T(1.0 / 36.0);
+        m2 = (v[2] - v[4]) * T(1.0 / 9.0) + ((v[5] + v[6]) - (v[7] + v[8])) * T(1.0 / 36.0);
+    }
 }
 
 // P^-1 applied to a raw-moment deviation dr, scaled by scale/w_a: the change

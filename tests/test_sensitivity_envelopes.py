@@ -51,3 +51,15 @@ def test_c3_scale_down_amplifies_a_one_time_fp32_perturbation():
     e = GOLD["c3_256x128_Ca0.3"]["1000"]["perturbed"]
     assert e["phi"] > 10 * 2.0 ** -24
     assert e["c"] > 100 * 2.0 ** -24
+
+
+def test_every_long_horizon_workload_has_its_envelope():
+    """Each workload and checkpoint that the long-horizon GPU checks use has
+    a stored envelope, positive for phi and c in both variants."""
+    need = {"c1": (500, 2000), "coupled_random": (150,), "c2": (5000, 10000, 20000),
+            "c3_Ca0.1": (1000, 5000), "c3_Ca0.3": (1000, 5000), "c3_Ca0.5": (1000, 5000)}
+    for key, ts in need.items():
+        for t in ts:
+            for variant in ("fp32", "perturbed"):
+                e = GOLD[key][str(t)][variant]
+                assert e["phi"] > 0 and e["c"] > 0, (key, t, variant, e)
