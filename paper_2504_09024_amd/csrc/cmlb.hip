@@ -114,6 +114,11 @@ void fill_consts(PhysConsts<T>& k, const SimDev& d) {
     k.qref_f = T(d.qref_f);
     k.inv_h = T(1.0 / d.scale_h);
     k.inv_g = T(1.0 / d.scale_g);
+    // the weight rounded to T first, then scaled by the power of two 1/scale_g
+    // (exact): v * wdec equals w_a * (v / scale_g) bit for bit
+    k.wdec0 = T(T(4.0 / 9.0) * T(1.0 / d.scale_g));
+    k.wdec1 = T(T(1.0 / 9.0) * T(1.0 / d.scale_g));
+    k.wdec5 = T(T(1.0 / 36.0) * T(1.0 / d.scale_g));
     k.scale_f = T(d.scale_f);
     k.scale_h = T(d.scale_h);
     k.scale_g = T(d.scale_g);

@@ -118,14 +118,15 @@ struct Buf<_Float16> {
 
 // Counter-based random words for the stochastic rounding, from the
 // MurmurHash3 32-bit finaliser fmix32.  A step has a key (the hash of the
-// step number); a node's seed for that step hashes its own hash combined
-// with the key, and the word for store k of the node is seed + k * 0x9E3779B9
-// (a Weyl sequence: one add each; its top bits, the ones the conversion
-// uses, are equidistributed).  The seed must be a hash of the (node, step)
-// pair.  The plain XOR of the two hashes relates every node's words at
-// consecutive steps by the same global XOR: the rounding then drifts the
-// inventories systematically (phi by 2.9e-3 over 5000 steps of a
-// 256x128x128 drop), where the hashed pair leaves random-walk noise (1e-5).
+// step number); a node's seed for that step is fmix32(node * 0x9E3779B9 +
+// key), and its store to direction q of any lattice uses seed + q *
+// 0x9E3779B9 (a Weyl sequence: one add per direction, shared by the node's
+// three lattices; its top bits, the ones the conversion uses, are
+// equidistributed).  The seed must be a hash of the (node, step) pair: the
+// XOR fmix32(node) ^ key relates every node's words at consecutive steps by
+// the same global XOR, and the rounding then drifts the inventories
+// systematically (phi by 2.9e-3 over 5000 steps of a 256x128x128 drop),
+// where a hashed pair leaves random-walk noise (1e-5).
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x85ebca6bu;
@@ -135,7 +136,7 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h;
 }
 __device__ __forceinline__ uint32_t node_step_seed(uint32_t node, uint32_t step_key) {
-    return fmix32(fmix32(node) ^ step_key);
+    return fmix32(node * 0x9E3779B9u + step_key);
 }
 __device__ __forceinline__ constexpr uint32_t weyl(int k) { return (uint32_t)k * 0x9E3779B9u; }
 

@@ -156,15 +156,18 @@ __device__ __forceinline__ void pull9_edge(__amdgpu_buffer_rsrc_t r, int lx, int
 // stored g values -> deviations d_a = w_a s_a / scale.  FP32 storage (scale
 // 1): w_a s_a as (9 w_a) s_a / 9, 9 w_a in {4, 1, 1/4} exact, with a
 // correctly rounded division, so the moments carry no common weight bias.
-template <class S, class T>
-__device__ __forceinline__ void to_dev(T v[9], T inv) {
+template <class S, class T, class KP>
+__device__ __forceinline__ void to_dev(T v[9], const KP& k) {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         if constexpr (std::is_same_v<S, float>) {
             v[a] = div_const<9>((a == 0 ? T(4) : (a < 5 ? T(1) : T(0.25))) * v[a]);
+        } else if constexpr (Store<S>::scaled) {
+            // one product with w_a / scale_g (scale_g a power of two)
+            v[a] = v[a] * (a == 0 ? k.wdec0 : (a < 5 ? k.wdec1 : k.wdec5));
         } else {
-            v[a] = Store<S>::scaled ? wgt<T>(a) * (v[a] * inv) : wgt<T>(a) * v[a];
+            v[a] = wgt<T>(a) * v[a];
         }
     }
 }
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         phiL[(iy + 2) * PW + lane + 2] = phv[j];
         cL[(iy + 1) * QW + lane + 1] = cv[j];
         if constexpr (CPL) {
-            to_dev<S, T>(qg[j], k.inv_g);
+            to_dev<S, T>(qg[j], k);
             mg[j] = moments6_nc(qg[j]);
             pL[(iy + 1) * QW + lane + 1] = mg[j].m0;
         }
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 cL[qi] = scalar_zeroth_nc<S>(q) * k.inv_h;
                 if constexpr (CPL) {
                     pull9_inner<S, T>(rG, vo, xp, xm, RB, q);
-                    to_dev<S, T>(q, k.inv_g);
+                    to_dev<S, T>(q, k);
                     pL[qi] = zeroth(q);
                 }
             }
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                 cL[qi] = scalar_zeroth_nc<S>(q) * k.inv_h;
                 if constexpr (CPL) {
                     pull9_edge<S, T, WALLS>(rG, hx, hy, nx, ny, nbx, BLK, q);
-                    to_dev<S, T>(q, k.inv_g);
+                    to_dev<S, T>(q, k);
                     pL[qi] = zeroth(q);
                 }
             }
@@ -582,12 +585,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
                     const int off = vo + q * RUN;
-                    Buf<S>::template store<CP>(wF, off, 0, qf[j][q], rs + weyl(3 * q));
-                    Buf<S>::template store<CP>(wH, off, 0, qh[j][q], rs + weyl(3 * q + 1));
+                    const uint32_t rq = rs + weyl(q);
+                    Buf<S>::template store<CP>(wF, off, 0, qf[j][q], rq);
+                    Buf<S>::template store<CP>(wH, off, 0, qh[j][q], rq);
                     if constexpr (CPL) {
                         T v = qg[j][q];
                         if (WALLS && wdir != 0 && EYa(q) == wdir) v += wcorr * T(EXa(q));
-                        Buf<S>::template store<CP>(wG, off, 0, v, rs + weyl(3 * q + 2));
+                        Buf<S>::template store<CP>(wG, off, 0, v, rq);
                     }
                 }
             }

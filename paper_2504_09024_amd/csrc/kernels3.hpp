@@ -875,7 +875,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                     for (int q = 0; q < 27; ++q)
                         Buf<S>::template store<CP>(w, vo, q * pb,
                                                    encode3_add<S>(m0, t[q], k.enc_f, q),
-                                                   rs + weyl(3 * q));
+                                                   rs + weyl(q));
                 }
                 // h: surfactant
                 {
@@ -890,7 +890,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                     for (int q = 0; q < 27; ++q)
                         Buf<S>::template store<CP>(w, vo, q * pb,
                                                    encode3_add<S>(m0, t[q], k.enc_h, q),
-                                                   rs + weyl(3 * q + 1));
+                                                   rs + weyl(q));
                 }
                 // g: flow
                 if constexpr (CPL) {
@@ -926,7 +926,7 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                     for (int q = 0; q < 27; ++q) {
                         T v = encode3<S>(t[q], k.enc_g, q);
                         if (WALLS && wdir != 0 && EYd(q) == wdir) v += wcorr * T(EXd(q));
-                        Buf<S>::template store<CP>(w, vo, q * pb, v, rs + weyl(3 * q + 2));
+                        Buf<S>::template store<CP>(w, vo, q * pb, v, rs + weyl(q));
                     }
                 }
             }

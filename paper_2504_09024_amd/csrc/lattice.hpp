@@ -40,6 +40,7 @@ enum { FLOW_NONE = 0, FLOW_PRESCRIBED = 1, FLOW_COUPLED = 2 };
 template <class T>
 struct PhysConsts {
     T inv_f, qref_f, inv_h, inv_g;    // storage decode: 1/scale, phi reference
+    T wdec0, wdec1, wdec5;            // w_a / scale_g for a = 0, 1..4, 5..8 (scaled g)
     T scale_f, scale_h, scale_g;      // storage encode scales (powers of two)
     T phi_a, phi_b, inv_dphi, phim;   // phase bounds, 1/(phi_a - phi_b), midpoint
     T theta_k, thetac_k;              // 4/W and 8/W
