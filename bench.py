@@ -492,7 +492,12 @@ def main():
         ctx = make_ctx(cmlb, sims, prec, stream, args.tile_rows, not args.no_graph,
                        not args.no_xcd_remap, args.tile_group, args.stores, args.tile_width)
     tuned = None
-    if not dim3 and not args.no_autotune and not args.tile_rows and args.stores == "auto":
+    if dim3 and not args.no_autotune and not args.tile3 and args.stores == "auto":
+        tuned = ctx.autotune(20)
+        log(f"[bench] autotuned launch: 64x{tuned[0]} columns over {tuned[1]} planes, "
+            f"{tuned[2]} stores")
+        tuned = (f"64x{tuned[0]} columns over {tuned[1]} planes", None, tuned[2])
+    elif not dim3 and not args.no_autotune and not args.tile_rows and args.stores == "auto":
         tuned = ctx.autotune(20)
         log(f"[bench] autotuned launch: {tuned[0]}x{tuned[1]} tiles, {tuned[2]} stores")
     gpu_s, wall_s = timed_run(ctx, args.steps, args.warmup, torch)
@@ -570,7 +575,8 @@ def main():
             "xcd_remap": not args.no_xcd_remap,
             "tile_group": args.tile_group if args.tile_group >= 0 else "default",
             "stores": args.stores,
-            "autotuned": (f"{tuned[0]}x{tuned[1]} tiles, {tuned[2]} stores" if tuned else None),
+            "autotuned": ((f"{tuned[0]}, {tuned[2]} stores" if tuned[1] is None else
+                           f"{tuned[0]}x{tuned[1]} tiles, {tuned[2]} stores") if tuned else None),
         },
         "roofline": {
             "bound": "hbm",

@@ -231,8 +231,9 @@ int cmlb_set_store_policy(cmlb_ctx* ctx, int32_t policy);
 
 /* Autotuner: advance the context's own simulations by `steps` (1..100000)
  * steps with every accepted tile shape under both store policies (default,
- * non-temporal), time each trial with HIP events on the context's stream,
- * and keep the fastest (written to *width, *rows, *policy when not NULL;
+ * non-temporal), time each trial with HIP events on the context's stream in
+ * the context's launch mode (graph replays when graphs are on, after an
+ * untimed warm-up that builds the graph), and keep the fastest (written to *width, *rows, *policy when not NULL;
  * policy as in cmlb_set_store_policy).  Every trial starts from a device
  * copy of the current state, which is restored afterwards together with the
  * step counter and fault flags: the simulations continue exactly as if no

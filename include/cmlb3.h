@@ -108,6 +108,20 @@ int cmlb3_launch_options(const cmlb3_ctx* ctx, int32_t* shapes, int32_t cap);
  * Results do not depend on it (bitwise). */
 int cmlb3_set_store_policy(cmlb3_ctx* ctx, int32_t policy);
 
+/* Autotuner, as cmlb_autotune: advance the context's own simulations by
+ * `steps` (1..100000) steps with every accepted collision shape (see
+ * cmlb3_launch_options) under both store policies (1 default, 2
+ * non-temporal), timed with HIP events on the context's stream in the
+ * context's launch mode (graph replays when graphs are on, after an untimed
+ * warm-up that builds the graph), and keep the fastest (written to *ty, *zs,
+ * *policy when not NULL).  Every trial starts from a device copy of the
+ * populations, restored afterwards together with the step counter and the
+ * fault flags: the simulations continue exactly as if no trial had run.
+ * Needs one population buffer's worth of free device memory (CMLB_ENOMEM
+ * otherwise).  Synchronous.  On error the previous launch configuration and
+ * the state are restored. */
+int cmlb3_autotune(cmlb3_ctx* ctx, int32_t steps, int32_t* ty, int32_t* zs, int32_t* policy);
+
 /* Replay steps through HIP graphs (1, default) or launch directly (0).
  * Results do not depend on it. */
 int cmlb3_set_use_graph(cmlb3_ctx* ctx, int32_t on);

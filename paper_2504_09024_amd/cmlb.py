@@ -51,7 +51,7 @@ EXPORTS3 = (
     "cmlb3_create", "cmlb3_init_fields", "cmlb3_step", "cmlb3_read_fields", "cmlb3_inventory",
     "cmlb3_get_populations", "cmlb3_set_populations", "cmlb3_fault_flags", "cmlb3_synchronize",
     "cmlb3_set_use_graph", "cmlb3_set_tile_shape", "cmlb3_launch_options",
-    "cmlb3_set_store_policy", "cmlb3_step_count",
+    "cmlb3_set_store_policy", "cmlb3_autotune", "cmlb3_step_count",
     "cmlb3_last_error", "cmlb3_destroy",
 )
 
@@ -140,6 +140,7 @@ def load(path: str = LIB_PATH):
     L.cmlb3_set_tile_shape.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.cmlb3_set_store_policy.argtypes = [vp, ctypes.c_int32]
     L.cmlb3_launch_options.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]
+    L.cmlb3_autotune.argtypes = [vp, ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 3
     L.cmlb3_step_count.argtypes = [vp]
     L.cmlb3_step_count.restype = ctypes.c_int64
     L.cmlb3_last_error.argtypes = [vp]
@@ -490,6 +491,15 @@ class Context3:
         buf = (ctypes.c_int32 * 32)()
         n = self.L.cmlb3_launch_options(self.h, buf, 32)
         return [(buf[2 * i], buf[2 * i + 1]) for i in range(max(n, 0))]
+
+    def autotune(self, steps=20):
+        """cmlb3_autotune: time every collision shape under both store
+        policies on these simulations (state restored); keeps and returns
+        the fastest as (ty, zs, store policy)."""
+        ty, zs, p = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.L.cmlb3_autotune(self.h, int(steps), ctypes.byref(ty), ctypes.byref(zs),
+                                          ctypes.byref(p)), "cmlb3_autotune")
+        return ty.value, zs.value, {1: "default", 2: "nt"}[p.value]
 
     @property
     def step_count(self):

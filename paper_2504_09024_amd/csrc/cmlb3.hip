@@ -737,6 +737,97 @@ int cmlb3_set_store_policy(cmlb3_ctx* c, int32_t policy) {
     return CMLB_OK;
 }
 
+int cmlb3_autotune(cmlb3_ctx* c, int32_t steps, int32_t* ty, int32_t* zs, int32_t* policy) {
+    if (!c || steps < 1 || steps > 100000) return CMLB_EINVAL;
+    for (int s = 0; s < c->n_sims; ++s)
+        if (!c->inited[s]) return fail3(c, CMLB_ESTATE, "simulation %d not initialised", s);
+    if (c->fault_seen) return fail3(c, CMLB_ERANGE, "a fault flag was raised earlier");
+    HIP3(c, hipStreamSynchronize(c->stream));
+    const int cur0 = c->cur;
+    const int64_t step0 = c->step;
+    const int ty0 = c->cty, zs0 = c->czs, p0 = c->store_policy;
+    int64_t dstep[2];
+    std::vector<int32_t> fault(c->n_sims);
+    HIP3(c, hipMemcpy(dstep, c->d_step, sizeof(dstep), hipMemcpyDeviceToHost));
+    HIP3(c, hipMemcpy(fault.data(), c->d_fault, sizeof(int32_t) * c->n_sims,
+                      hipMemcpyDeviceToHost));
+    void* save = nullptr;
+    if (hipMalloc(&save, c->pop_bytes) != hipSuccess)
+        return fail3(c, CMLB_ENOMEM, "no device memory for the autotuner's state copy");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = CMLB_OK;
+    // the moment arrays are recomputed from the populations every step, so
+    // the populations, the step counter and the fault flags are the state
+    auto restore = [&]() -> int {
+        c->cur = cur0;
+        c->step = step0;
+        HIP3(c, hipMemcpyAsync(c->pop[cur0], save, c->pop_bytes, hipMemcpyDeviceToDevice,
+                               c->stream));
+        HIP3(c, hipMemcpyAsync(c->d_step, dstep, sizeof(dstep), hipMemcpyHostToDevice,
+                               c->stream));
+        HIP3(c, hipMemcpyAsync(c->d_fault, fault.data(), sizeof(int32_t) * c->n_sims,
+                               hipMemcpyHostToDevice, c->stream));
+        HIP3(c, hipStreamSynchronize(c->stream));
+        return CMLB_OK;
+    };
+    float best = 0.f;
+    int bty = 0, bzs = 0, bp = 0;
+    do {
+        if (hipMemcpyAsync(save, c->pop[cur0], c->pop_bytes, hipMemcpyDeviceToDevice,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = fail3(c, CMLB_EDEVICE, "autotuner set-up failed");
+            break;
+        }
+        for (int i = 0; i < N_SHAPES3 && rc == CMLB_OK; ++i)
+            for (int pol = 1; pol <= 2 && rc == CMLB_OK; ++pol) {
+                c->cty = SHAPES3[i].ty;
+                c->czs = SHAPES3[i].zs;
+                c->store_policy = pol;
+                if ((rc = build_ctiles3(c)) != CMLB_OK) break;
+                // untimed: builds the graph the timed steps replay
+                if ((rc = cmlb3_step(c, GRAPH_STEPS3 + 2)) != CMLB_OK) break;
+                if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = CMLB_EDEVICE; break; }
+                if ((rc = cmlb3_step(c, steps)) != CMLB_OK) break;
+                float ms = 0.f;
+                if (hipEventRecord(e1, c->stream) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    rc = fail3(c, CMLB_EDEVICE, "autotuner timing failed");
+                    break;
+                }
+                if (bty == 0 || ms < best) {
+                    best = ms;
+                    bty = SHAPES3[i].ty;
+                    bzs = SHAPES3[i].zs;
+                    bp = pol;
+                }
+                if ((rc = restore()) != CMLB_OK) break;
+            }
+    } while (false);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc != CMLB_OK) {
+        (void)restore();
+        (void)hipFree(save);
+        c->cty = ty0;
+        c->czs = zs0;
+        c->store_policy = p0;
+        (void)build_ctiles3(c);
+        return rc;
+    }
+    (void)hipFree(save);
+    c->cty = bty;
+    c->czs = bzs;
+    c->store_policy = bp;
+    if ((rc = build_ctiles3(c)) != CMLB_OK) return rc;
+    if (ty) *ty = bty;
+    if (zs) *zs = bzs;
+    if (policy) *policy = bp;
+    return CMLB_OK;
+}
+
 int cmlb3_set_use_graph(cmlb3_ctx* c, int32_t on) {
     if (!c) return CMLB_EINVAL;
     c->use_graph = on ? 1 : 0;

@@ -111,6 +111,27 @@ def test_tile_shapes_bitwise3(gpu_lib, prec):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_autotune3_leaves_the_run_unchanged(gpu_lib, prec):
+    """The 3D autotuner's trials leave no trace: 10 steps, autotune, 20 steps
+    equals 30 plain steps bit for bit, the step counter is kept, and the
+    chosen shape is one of the accepted ones."""
+    p, fl = CASES3["coupled3"][0]()
+    a = ctx3(p, fl, prec)
+    a.step(10)
+    ty, zs, pol = a.autotune(5)
+    assert (ty, zs) in a.launch_options() and pol in ("default", "nt")
+    assert a.step_count == 10
+    a.step(20)
+    b = ctx3(p, fl, prec)
+    b.step(30)
+    for x, y in zip(a.get_populations(0), b.get_populations(0)):
+        assert np.array_equal(x, y)
+    assert a.fault_flags(0) == 0
+    a.close()
+    b.close()
+
+
 def test_store_policies_bitwise3(gpu_lib):
     """Default and non-temporal population stores give identical results."""
     p, fl = CASES3["coupled3"][0]()
