@@ -378,6 +378,8 @@ def main():
                     help="keep the library's default launch shape instead of timing the options")
     ap.add_argument("--no-forms", action="store_true", help="skip the other storage forms")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--launch-costs", action="store_true",
+                    help="print the cost of a grid barrier and of a graph kernel boundary")
     ap.add_argument("--copy-bw", default="", metavar="MIB,MIB,...",
                     help="only time torch device copies of these sizes (GB/s read + write)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -428,6 +430,16 @@ def main():
     tstream = torch.cuda.Stream()
     torch.cuda.set_stream(tstream)
     stream = tstream.cuda_stream
+
+    if args.launch_costs:
+        # what separates time steps costs: a grid barrier inside one
+        # cooperative launch against a kernel boundary inside a replayed graph
+        out = {}
+        for blocks in (32, 64, 128, 256):
+            sync_us, node_us = cmlb.launch_costs(blocks, 2048)
+            out[str(blocks)] = {"grid_sync_us": round(sync_us, 3), "graph_node_us": round(node_us, 3)}
+        print(json.dumps({"launch_costs_by_workgroups": out}), flush=True)
+        return
 
     if args.copy_bw:
         # device-to-device copy bandwidth (read + write bytes) at working

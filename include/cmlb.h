@@ -247,6 +247,18 @@ int cmlb_autotune(cmlb_ctx* ctx, int32_t steps, int32_t* width, int32_t* rows, i
  * for plain row-major order (default).  Results do not depend on it. */
 int cmlb_set_tile_order(cmlb_ctx* ctx, int32_t group);
 
+/* Measurement aid, not part of the method: the cost of the two ways of
+ * separating time steps on the current device.  *us_grid_sync: microseconds
+ * per grid-wide barrier (HIP cooperative groups) among `blocks` workgroups of
+ * 256 threads in one cooperative launch looping `iters` times, the barrier a
+ * multi-step persistent kernel would need between steps.  *us_graph_node:
+ * microseconds per kernel in a HIP graph of 16 dependent launches of an
+ * empty kernel of `blocks` workgroups, replayed iters / 16 times, the
+ * separation the step graphs use.  blocks 1..1024 (CMLB_EDEVICE when the
+ * runtime cannot make the grid resident), iters a multiple of 16 in
+ * 16..10^6.  Synchronous, on a private stream; allocates a few bytes. */
+int cmlb_launch_costs(int32_t blocks, int32_t iters, double* us_grid_sync, double* us_graph_node);
+
 /* Measurement aid, not part of the method: copy `bytes` of device memory
  * from src to dst on hip_stream (NULL = the default stream), asynchronously,
  * with 16-byte vector loads and stores, four per thread.  nontemporal = 1

@@ -44,7 +44,8 @@ EXPORTS = (
     "cmlb_synchronize", "cmlb_set_tile_rows", "cmlb_set_tile_shape", "cmlb_launch_options",
     "cmlb_set_use_graph",
     "cmlb_set_xcd_remap", "cmlb_set_tile_order", "cmlb_set_store_policy", "cmlb_autotune",
-    "cmlb_copy", "cmlb_copy_planes", "cmlb_step_count", "cmlb_num_sims", "cmlb_last_error", "cmlb_destroy",
+    "cmlb_copy", "cmlb_copy_planes", "cmlb_launch_costs", "cmlb_step_count", "cmlb_num_sims",
+    "cmlb_last_error", "cmlb_destroy",
 )
 
 EXPORTS3 = (
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH):
     L.cmlb_autotune.argtypes = [vp, ctypes.c_int32, ip, ip, ip]
     L.cmlb_copy.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp]
     L.cmlb_copy_planes.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp]
+    L.cmlb_launch_costs.argtypes = [ctypes.c_int32, ctypes.c_int32, dp, dp]
     L.cmlb_step_count.argtypes = [vp]
     L.cmlb_step_count.restype = ctypes.c_int64
     L.cmlb_num_sims.argtypes = [vp]
@@ -177,6 +179,19 @@ def device_copy_planes(src_ptr: int, dst_ptr: int, plane_bytes: int, planes: int
                             ctypes.c_void_p(stream) if stream else None)
     if rc != 0:
         raise CmlbError(rc, "cmlb_copy_planes")
+
+
+def launch_costs(blocks: int = 64, iters: int = 2048):
+    """cmlb_launch_costs: (microseconds per grid-wide barrier in one
+    cooperative launch, microseconds per kernel of a replayed graph), both
+    with `blocks` workgroups of 256 threads.  A measurement aid, not part of
+    the method."""
+    L = load()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    rc = L.cmlb_launch_costs(int(blocks), int(iters), ctypes.byref(a), ctypes.byref(b))
+    if rc != 0:
+        raise CmlbError(rc, "cmlb_launch_costs")
+    return a.value, b.value
 
 
 def _dptr(a):

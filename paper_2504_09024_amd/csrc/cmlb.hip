@@ -1,6 +1,7 @@
 // Host runtime and C ABI (include/cmlb.h) of the MI355X coupled
 // central-moment LB step.  Owns device buffers, the tile tables, the step
 // counter and the HIP graphs; every step runs in the kernels of kernels.hpp.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,6 +57,21 @@ __global__ __launch_bounds__(256) void k_copy_planes(const f32x4* __restrict__ a
         if (NT) __builtin_nontemporal_store(v[q], &b[q * n4 + i]);
         else b[q * n4 + i] = v[q];
     }
+}
+// Launch-cost probes (cmlb_launch_costs): a loop of grid barriers in one
+// cooperative launch, and a kernel that does nothing (its store is never
+// taken: no thread index reaches 2^20).
+__global__ __launch_bounds__(256) void k_grid_sync_loop(int32_t iters, float* sink) {
+    cooperative_groups::grid_group g = cooperative_groups::this_grid();
+    float acc = float(threadIdx.x);
+    for (int i = 0; i < iters; ++i) {
+        acc = acc * 0.5f + 1.0f;
+        g.sync();
+    }
+    if (threadIdx.x >= (1u << 20)) sink[blockIdx.x] = acc;
+}
+__global__ __launch_bounds__(256) void k_nothing(float* sink) {
+    if (threadIdx.x >= (1u << 20)) sink[blockIdx.x] = 1.0f;
 }
 }  // namespace cmlb
 
@@ -1059,6 +1075,73 @@ int cmlb_set_tile_order(cmlb_ctx* c, int32_t group) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->tile_group = group;
     return build_tiles(c);
+}
+
+int cmlb_launch_costs(int32_t blocks, int32_t iters, double* us_grid_sync, double* us_graph_node) {
+    if (blocks < 1 || blocks > 1024 || iters < 16 || iters > 1000000 || (iters % 16) ||
+        !us_grid_sync || !us_graph_node)
+        return CMLB_EINVAL;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    float* sink = nullptr;
+    int rc = CMLB_OK;
+    auto ok = [&](hipError_t e) {
+        if (e != hipSuccess && rc == CMLB_OK) rc = CMLB_EDEVICE;
+        return rc == CMLB_OK;
+    };
+    do {
+        if (!ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) || !ok(hipEventCreate(&e0)) ||
+            !ok(hipEventCreate(&e1)) || !ok(hipMalloc(&sink, sizeof(float) * blocks)))
+            break;
+        // (1) a cooperative launch whose workgroups meet at a grid barrier
+        // `iters` times; the runtime refuses a grid that cannot be resident
+        int32_t n = iters;
+        void* args[] = {&n, &sink};
+        if (!ok(hipLaunchCooperativeKernel((void*)cmlb::k_grid_sync_loop, dim3(blocks), dim3(256),
+                                           args, 0, s)) ||
+            !ok(hipStreamSynchronize(s)) || !ok(hipEventRecord(e0, s)) ||
+            !ok(hipLaunchCooperativeKernel((void*)cmlb::k_grid_sync_loop, dim3(blocks), dim3(256),
+                                           args, 0, s)) ||
+            !ok(hipEventRecord(e1, s)) || !ok(hipEventSynchronize(e1)))
+            break;
+        float ms = 0.f;
+        if (!ok(hipEventElapsedTime(&ms, e0, e1))) break;
+        *us_grid_sync = 1e3 * ms / iters;
+        // (2) a graph of 16 dependent launches of a kernel that does nothing,
+        // replayed iters / 16 times: the per-step cost of the step graphs
+        if (!ok(hipGraphCreate(&g, 0))) break;
+        hipGraphNode_t prev = nullptr;
+        for (int i = 0; i < 16 && rc == CMLB_OK; ++i) {
+            hipKernelNodeParams np{};
+            void* kargs[] = {&sink};
+            np.func = (void*)cmlb::k_nothing;
+            np.gridDim = dim3(blocks);
+            np.blockDim = dim3(256);
+            np.kernelParams = kargs;
+            hipGraphNode_t node;
+            if (!ok(hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &np)))
+                break;
+            prev = node;
+        }
+        if (rc != CMLB_OK || !ok(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0)) ||
+            !ok(hipGraphLaunch(ge, s)) || !ok(hipStreamSynchronize(s)) ||
+            !ok(hipEventRecord(e0, s)))
+            break;
+        for (int i = 0; i < iters / 16 && rc == CMLB_OK; ++i) ok(hipGraphLaunch(ge, s));
+        if (rc != CMLB_OK || !ok(hipEventRecord(e1, s)) || !ok(hipEventSynchronize(e1)) ||
+            !ok(hipEventElapsedTime(&ms, e0, e1)))
+            break;
+        *us_graph_node = 1e3 * ms / iters;
+    } while (false);
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    if (sink) (void)hipFree(sink);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    return rc;
 }
 
 int cmlb_copy(const void* src, void* dst, int64_t bytes, int32_t nontemporal, void* hip_stream) {
