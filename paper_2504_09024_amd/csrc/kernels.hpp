@@ -55,11 +55,6 @@ __device__ __forceinline__ void scalar_moments_nc(const T v[9], T& m0, T& m1, T&
 #pragma clang fp contract(off)
     scalar_moments<T, std::is_same_v<S, float>>(v, m0, m1, m2);
 }
-template <class T>
-__device__ __forceinline__ void scalar_moments_split_nc(const T v[9], T& v0, T& d, T& m1, T& m2) {
-#pragma clang fp contract(off)
-    scalar_moments_split(v, v0, d, m1, m2);
-}
 template <class S, class T>
 __device__ __forceinline__ T scalar_zeroth_nc(const T v[9]) {
 #pragma clang fp contract(off)
@@ -242,11 +237,6 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     __shared__ T pL[CPL ? QH * QW : 1];
     __shared__ T nxL[CPL ? QH * QW : 1];
     __shared__ T nyL[CPL ? QH * QW : 1];
-    // FP32 storage: the rest d of phi's zeroth moment and phi's first moments
-    // of each own node, from phase 1 to phase 3 (in LDS rather than in
-    // registers across the phases: the split of the zeroth moment would
-    // otherwise push several launch shapes past 128 VGPRs)
-    __shared__ T phdL[std::is_same_v<S, float> ? 3 * NT * NPT : 1];
 
     // Workgroups are dispatched round-robin over the 8 XCDs (each with its
     // own L2): give XCD k the contiguous tile range [k*per, (k+1)*per) so that
@@ -307,10 +297,6 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     if constexpr (LOAD_PRIO) __builtin_amdgcn_s_setprio(2);
     T qf[NPT][9], qh[NPT][9], qg[CPL ? NPT : 1][9];
     T phv[NPT], cv[NPT], phn[NPT], chn[NPT], jfx[NPT], jfy[NPT], jhx[NPT], jhy[NPT];
-    // FP32 storage: phn holds v_0 and phdL the rest d of phi's zeroth moment
-    // (scalar_moments_split).  The surfactant keeps its one-number zeroth
-    // moment: its inventory drifts by 3e-8 in the same 5000 steps.
-    constexpr bool SPLIT = std::is_same_v<S, float>;
     Raw6<T> mg[CPL ? NPT : 1];
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
@@ -333,27 +319,13 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
 #pragma unroll
     for (int j = 0; j < NPT; ++j) {
         const int iy = wave * NPT + j;
-        if constexpr (SPLIT) {
-            T d, m1, m2;
-            scalar_moments_split_nc(qf[j], phn[j], d, m1, m2);
-            scalar_moments_nc<S>(qh[j], chn[j], jhx[j], jhy[j]);
-            phdL[j * NT + tid] = d;
-            phdL[(NPT + j) * NT + tid] = m1 * k.inv_f;
-            phdL[(2 * NPT + j) * NT + tid] = m2 * k.inv_f;
-            // the same bits as the halo's zeroth moment v_0 + d
-            phv[j] = (phn[j] + d) * k.inv_f + k.qref_f;
-            cv[j] = chn[j] * k.inv_h;
-        } else {
-            scalar_moments_nc<S>(qf[j], phn[j], jfx[j], jfy[j]);
-            scalar_moments_nc<S>(qh[j], chn[j], jhx[j], jhy[j]);
-            // true zeroth and first moments
-            phv[j] = phn[j] * k.inv_f + k.qref_f;
-            cv[j] = chn[j] * k.inv_h;
-        }
-        if constexpr (!SPLIT) {
-            jfx[j] *= k.inv_f;
-            jfy[j] *= k.inv_f;
-        }
+        scalar_moments_nc<S>(qf[j], phn[j], jfx[j], jfy[j]);
+        scalar_moments_nc<S>(qh[j], chn[j], jhx[j], jhy[j]);
+        // true zeroth and first moments
+        phv[j] = phn[j] * k.inv_f + k.qref_f;
+        cv[j] = chn[j] * k.inv_h;
+        jfx[j] *= k.inv_f;
+        jfy[j] *= k.inv_f;
         jhx[j] *= k.inv_h;
         jhy[j] *= k.inv_h;
         phiL[(iy + 2) * PW + lane + 2] = phv[j];
@@ -459,11 +431,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
         const bool valid = gx < nx && gy < ny;
         const int pidx = (iy + 2) * PW + lane + 2;
         const int qidx = (iy + 1) * QW + lane + 1;
-        // (recomputed rather than kept from phase 1: no more live registers
-        // than without the split)
-        const T phd = SPLIT ? phdL[(SPLIT ? j : 0) * NT + tid] : T(0);
-        const T phi = SPLIT ? (phn[j] + phd) * k.inv_f + k.qref_f : phv[j];
-        const T c = cv[j];
+        const T phi = phv[j], c = cv[j];
         T gpx, gpy;
         lds_grad<T, PW>(phiL, pidx, gpx, gpy);
         const T gm2 = gpx * gpx + gpy * gpy;
@@ -549,22 +517,9 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
             // moment (storage units) + P^-1 of the raw-moment deviation.
             T r[9];
             {
-                const T jx = SPLIT ? phdL[(NPT + j) * NT + tid] : jfx[j];
-                const T jy = SPLIT ? phdL[(2 * NPT + j) * NT + tid] : jfy[j];
-                const T k1 = (T(1) - k.omega_k) * (jx - ux * phi) + k.omega_k * k.M_phi * theta * nxv;
-                const T k2 = (T(1) - k.omega_k) * (jy - uy * phi) + k.omega_k * k.M_phi * theta * nyv;
+                const T k1 = (T(1) - k.omega_k) * (jfx[j] - ux * phi) + k.omega_k * k.M_phi * theta * nxv;
+                const T k2 = (T(1) - k.omega_k) * (jfy[j] - uy * phi) + k.omega_k * k.M_phi * theta * nyv;
                 scalar_post_dev<T, MOV>(phi, k1, k2, ux, uy, r);
-                if constexpr (SPLIT) {
-                    // base v_0; d enters as the rest moments of a uniform
-                    // d / scale_f (1, 0, 0, cs2, cs2, 0, 0, 0, cs2^2), which
-                    // P^-1 spreads evenly: every value becomes v_0 + (d +
-                    // change), each rounded once
-                    const T dd = phd * k.inv_f;
-                    r[0] += dd;
-                    r[3] += K<T>::cs2 * dd;
-                    r[4] += K<T>::cs2 * dd;
-                    r[8] += K<T>::cs4 * dd;
-                }
                 pinv_dev_add(r, k.scale_f, phn[j], qf[j]);
             }
             // h: interface-bound surfactant (Sec. 3)

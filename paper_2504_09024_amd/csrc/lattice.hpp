@@ -172,23 +172,6 @@ __device__ __forceinline__ void scalar_moments(const T v[9], T& m0, T& m1, T& m2
     }
 }
 
-// FP32 storage: the zeroth moment kept as the pair (v_0, d), m0 = v_0 + d
-// with d = sum_a w_a (v_a - v_0), instead of one FP32 number.  The
-// post-collision values are v_0 + (d + change_a), so each carries its own
-// rounding: one rounded m0 shared by all nine would move the node's whole
-// content by that rounding every step (phi gained 1e-5 in 5000 steps of the
-// 1024 x 512 shear drop, against 4e-7 from rounding each stored value).
-template <class T>
-__device__ __forceinline__ void scalar_moments_split(const T v[9], T& v0, T& d, T& m1, T& m2) {
-    const T v4 = T(4) * v[0];
-    const T A = (v[1] + v[2]) + (v[3] + v[4]);
-    const T B = (v[5] + v[6]) + (v[7] + v[8]);
-    v0 = v[0];
-    d = div_const<36>(T(4) * (A - v4) + (B - v4));
-    m1 = div_const<36>(T(4) * (v[1] - v[3]) + ((v[5] - v[6]) + (v[8] - v[7])));
-    m2 = div_const<36>(T(4) * (v[2] - v[4]) + ((v[5] + v[6]) - (v[7] + v[8])));
-}
-
 // P^-1 applied to a raw-moment deviation dr, scaled by scale/w_a: the change
 // of the stored values relative to the rest equilibrium of the node's own
 // zeroth moment.
