@@ -288,12 +288,14 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
     const int lx = inner ? (gx < nx ? gx : gx - nx) : wrap_coord(gx, nx);
 
     // ---------------- phase 1: own nodes -----------------------------------
-    // FP32 storage: the wave issues its own pulls at raised priority, so a
+    // FP32 storage with non-temporal stores (working sets beyond the
+    // Infinity Cache): the wave issues its own pulls at raised priority, so a
     // wave entering the step gets its loads out ahead of the arithmetic of
-    // the other waves on its SIMD (64-drop batch: +4% in FP32; the same in
-    // FP16 or FP64 costs 8-10%, there the arithmetic is the scarcer
-    // resource, so they keep the default priority).
-    constexpr bool LOAD_PRIO = std::is_same_v<S, float>;
+    // the other waves on its SIMD (64-drop batch: +4%).  The same costs
+    // 8-10% in FP16 or FP64, where the arithmetic is the scarcer resource,
+    // and 2.7% on the cache-resident 1024x512 drop (default stores), so
+    // those keep the default priority.
+    constexpr bool LOAD_PRIO = std::is_same_v<S, float> && NTS;
     if constexpr (LOAD_PRIO) __builtin_amdgcn_s_setprio(2);
     T qf[NPT][9], qh[NPT][9], qg[CPL ? NPT : 1][9];
     T phv[NPT], cv[NPT], phn[NPT], chn[NPT], jfx[NPT], jfy[NPT], jhx[NPT], jhy[NPT];
