@@ -26,10 +26,15 @@
 // q_ref = phi_m (FP16 f), P_ref = rho_b cs2 (g), 0 otherwise.  Collisions
 // work on deviations from the rest state, so FP32 keeps its relative
 // precision on small velocities, and outputs are the node's own zeroth
-// moment plus a deviation, so a resting bulk node is a fixed point.
+// moment plus a deviation, so a resting bulk node is a fixed point.  With FP32
+// storage the weights enter as 27 w_a (exact) with one correctly rounded
+// division by 27 per moment, and the flow collision changes the momentum by
+// exactly cs2 F, as in 2D.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "device_common.hpp"
 
@@ -37,6 +42,7 @@ namespace cmlb3 {
 
 using cmlb::Buf;
 using cmlb::CPOL_NT;
+using cmlb::div_const;
 using cmlb::fmix32;
 using cmlb::log_;
 using cmlb::make_rsrc;
@@ -196,18 +202,32 @@ __device__ __forceinline__ void pull27(__amdgpu_buffer_rsrc_t r, int pb, int x, 
 
 // zeroth (exact for a uniform node: s0 + sum w (s_a - s0)) and first
 // moments of stored scalar-lattice values, storage units
+// 27 w_a: 8, 2, 1/2, 1/8 for 0, 1, 2, 3 non-zero components (exact)
 template <class T>
+__device__ __forceinline__ constexpr T wgt3x27(int a) {
+    return T(8) / T(1 << (2 * ((a % 3 != 0) + ((a / 3) % 3 != 0) + (a / 9 != 0))));
+}
+// EXACT (FP32 storage): the weights enter as 27 w_a (exact) and one
+// correctly rounded division by 27 per moment, not as products with the
+// rounded weights, whose common bias would scale the moments every step
+template <class T, bool EXACT = false>
 __device__ __forceinline__ void scalar_moments27(const T v[27], T& m0, T& jx, T& jy, T& jz) {
 #pragma clang fp contract(off)
     const T s0 = v[0];
     T z = T(0), x = T(0), y = T(0), w = T(0);
 #pragma unroll
     for (int a = 1; a < 27; ++a) {
-        const T d = wgt3<T>(a) * (v[a] - s0);
+        const T d = EXACT ? wgt3x27<T>(a) * (v[a] - s0) : wgt3<T>(a) * (v[a] - s0);
         z += d;
         if (EXd(a)) x += EXd(a) > 0 ? d : -d;
         if (EYd(a)) y += EYd(a) > 0 ? d : -d;
         if (EZd(a)) w += EZd(a) > 0 ? d : -d;
+    }
+    if constexpr (EXACT) {
+        z = div_const<27>(z);
+        x = div_const<27>(x);
+        y = div_const<27>(y);
+        w = div_const<27>(w);
     }
     m0 = s0 + z;
     jx = x;
@@ -261,14 +281,14 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
     }
 #pragma unroll
     for (int q = 0; q < 27; ++q) v[q] = T(Buf<S>::widen(sf[q]));
-    scalar_moments27(v, fm[0], fm[1], fm[2], fm[3]);
+    scalar_moments27<T, std::is_same_v<S, float>>(v, fm[0], fm[1], fm[2], fm[3]);
     if constexpr (AHEAD) {
 #pragma unroll
         for (int q = 0; q < 27; ++q) v[q] = T(Buf<S>::widen(sh[q]));
     } else {
         pull27<S, WALLS>(make_rsrc(srcb + lb, lb), pb, x, y, z, nx, ny, nz, inner, v);
     }
-    scalar_moments27(v, hm[0], hm[1], hm[2], hm[3]);
+    scalar_moments27<T, std::is_same_v<S, float>>(v, hm[0], hm[1], hm[2], hm[3]);
     T r0 = T(0), r1[3] = {T(0), T(0), T(0)}, r2[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     if constexpr (CPL) {
         if constexpr (AHEAD) {
@@ -282,7 +302,8 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
 #pragma clang fp contract(off)
 #pragma unroll
         for (int q = 0; q < 27; ++q) {
-            const T d = Store<S>::scaled ? wgt3<T>(q) * (v[q] * k.inv_g) : wgt3<T>(q) * v[q];
+            const T d = std::is_same_v<S, float> ? wgt3x27<T>(q) * v[q]
+                        : (Store<S>::scaled ? wgt3<T>(q) * (v[q] * k.inv_g) : wgt3<T>(q) * v[q]);
             const int ex = EXd(q), ey = EYd(q), ez = EZd(q);
             r0 += d;
             if (ex) r1[0] += ex > 0 ? d : -d;
@@ -294,6 +315,13 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
             if (ex && ey) r2[3] += ex * ey > 0 ? d : -d;
             if (ex && ez) r2[4] += ex * ez > 0 ? d : -d;
             if (ey && ez) r2[5] += ey * ez > 0 ? d : -d;
+        }
+        if constexpr (std::is_same_v<S, float>) {
+            r0 = div_const<27>(r0);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) r1[i] = div_const<27>(r1[i]);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) r2[i] = div_const<27>(r2[i]);
         }
         }
     }
@@ -450,7 +478,6 @@ __device__ __forceinline__ void flow_dev27(const T eta2[6], T dP, T rho, T ux, T
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) t[dg[i]] = dd[i] + third * trt;
-    inverse27(t, ux, uy, uz);
 }
 
 // Isotropic D3Q27 stencils at in-plane index idx of three LDS planes
@@ -906,6 +933,16 @@ __global__ __launch_bounds__(TY * 64, (Occ3<T, TY>::waves_per_eu)) void k_collid
                     eta2[4] = r2[4] - u[0] * j[2] - u[2] * j[0] + u[0] * u[2] * r0;
                     eta2[5] = r2[5] - u[1] * j[2] - u[2] * j[1] + u[1] * u[2] * r0;
                     flow_dev27<T>(eta2, dP, rho, ux, uy, uz, fp, ft, gam, k.omega_zeta, om_nu, t);
+                    if constexpr (std::is_same_v<S, float>) {
+                        // the collision changes the momentum by exactly cs2 F:
+                        // raw first moment j + cs2 F, so the central one is
+                        // that minus u t0 (no rounding of u in the momentum)
+                        const T cs2 = C3<T>::cs2;
+                        t[1] = (j[0] + cs2 * ft[0]) - ux * t[0];
+                        t[3] = (j[1] + cs2 * ft[1]) - uy * t[0];
+                        t[9] = (j[2] + cs2 * ft[2]) - uz * t[0];
+                    }
+                    inverse27(t, ux, uy, uz);
                     // moving wall: slots of directions pointing into the wall
                     // are pulled back by this node next step; add
                     // 2 rho (e_opp . u_w)

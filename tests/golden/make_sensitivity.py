@@ -19,7 +19,8 @@ between base and each of the others at every checkpoint.  The C3 coupled
 shear drop (1024x512, Sec. 4.3 set-up, Re = 0.1, Ca in {0.1, 0.3, 0.5},
 E = 0.2, c0 = 0.3) is checked at 1000 and 5000 steps, the C2 drop in the
 time-reversing vortex (512x512, Sec. 4.2 extended; T = 20000) at T/4, T/2 and
-T, a 256x128 scale-down of C3 at 1000 steps, the C1 static drop (128x128,
+T, the 3D C5 drop in shear scaled down to 64x32x32 (R = 8) at 1000 and 5000
+steps, a 256x128 scale-down of C3 at 1000 steps, the C1 static drop (128x128,
 Sec. 4.1 set-up) at 500 and 2000 steps and the random-field parity case
 coupled_random at 150 steps (the last three cheap enough for the CPU suite
 to recompute).
@@ -64,6 +65,8 @@ def workloads():
     for ca in (0.3, 0.1, 0.5):
         out[f"c3_Ca{ca}"] = (lambda ca=ca: W.shear_drop(Ca=ca), (1000, 5000))
     out["c2"] = (lambda: W.vortex_drop(), (5000, 10000, 20000))
+    # 3D: the C5 shear drop scaled down by four in every direction (R = 8)
+    out["c5_64x32x32"] = (lambda: W.shear_drop3(nx=64, ny=32, nz=32, R=8.0), (1000, 5000))
     return out
 
 
@@ -84,16 +87,22 @@ def _round_plane(q, w, ref):
 
 def round_storage_fp32(o, P_ref, pool):
     """Round the oracle's populations in place to the FP32 storage form, one
-    direction plane per task."""
-    w = oracle.weights()
+    direction plane per task (D2Q9 or D3Q27)."""
+    w = oracle.weights3() if o.f.shape[0] == 27 else oracle.weights()
     jobs = [(q[a], w[a], ref) for q, ref in ((o.f, 0.0), (o.h, 0.0), (o.g, P_ref))
-            if q is not None for a in range(9)]
+            if q is not None for a in range(len(w))]
     list(pool.map(lambda j: _round_plane(*j), jobs))
 
 
 def make_sim(p, fl, phi):
+    if "nz" in p:
+        return oracle.OracleSim3(oracle.make_params3(**p), phi, fl["c"], fl.get("ux"),
+                                 fl.get("uy"), fl.get("uz"), fl.get("P"))
     return oracle.OracleSim(oracle.make_params(**p), phi, fl["c"], fl.get("ux"), fl.get("uy"),
                             fl.get("P"))
+
+
+FIELDS = ("phi", "c", "ux", "uy", "uz")
 
 
 def run_variant(p, fl, variant, checkpoints, label=""):
@@ -114,7 +123,7 @@ def run_variant(p, fl, variant, checkpoints, label=""):
             if o.t % 1000 == 0:
                 print(f"[sensitivity] {label} {variant} t={o.t}", flush=True)
         fl_t = o.fields()
-        out[t_end] = {k: fl_t[k].copy() for k in ("phi", "c", "ux", "uy")}
+        out[t_end] = {k: fl_t[k].copy() for k in FIELDS if k in fl_t}
     return out
 
 
@@ -126,15 +135,16 @@ def rel(a, b):
 
 
 def diffs(base, other):
+    uk = [k for k in ("ux", "uy", "uz") if k in base]
     return {"phi": rel(other["phi"], base["phi"]), "c": rel(other["c"], base["c"]),
-            "u": rel(np.stack([other["ux"], other["uy"]]), np.stack([base["ux"], base["uy"]]))}
+            "u": rel(np.stack([other[k] for k in uk]), np.stack([base[k] for k in uk]))}
 
 
 def cached_run(cache, key, p, fl, variant, checkpoints):
     path = os.path.join(cache, f"{key}_{variant}.npz")
     if os.path.exists(path):
         z = np.load(path)
-        return {t: {k: z[f"{t}_{k}"] for k in ("phi", "c", "ux", "uy")} for t in checkpoints}
+        return {t: {k: z[f"{t}_{k}"] for k in FIELDS if f"{t}_{k}" in z} for t in checkpoints}
     t0 = time.perf_counter()
     res = run_variant(p, fl, variant, checkpoints, key)
     np.savez(path, **{f"{t}_{k}": v for t, d in res.items() for k, v in d.items()})

@@ -159,3 +159,54 @@ def test_c3_one_step_from_gpu_state_after_5000(oracle_mod, gpu_lib, prec, tol):
         dm = d.max() / np.abs(b).max()
         print(f"C3 {prec} one step after 5000, {name}: {dm:.2e} (everywhere {d_all:.2e})")
         assert dm <= tol, (name, dm)
+
+
+# FP32 arithmetic floor of the 3D capillary velocity at R = 8 (relative L2
+# of u): the error sits at the interface (no part of it is a change of the
+# sheared bulk profile), is 1.3e-5 after 1000 steps and 1.2e-5 after 5000,
+# and comes from the FP32 surface-tension force on a drop of radius 8 (curvature
+# from FP32 normals that turn by 1/8 per node); the storage rounding that
+# the oracle's envelope measures moves u by only 2.9e-8 at 1000 steps
+U_FLOOR_3D = 2e-5
+
+
+def test_c5_scaled_fp32_within_envelope_1000_and_5000_steps(gpu_lib):
+    """The 3D drop in shear (C5 set-up) scaled down by four in every
+    direction, 64 x 32 x 32 with R = 8, FP32 against FP64 after 1000 and
+    5000 steps, against the 3D oracle's own envelopes at that size (the
+    full-size run is beyond the CPU oracle's reach at these horizons).
+    Measured: phi 1.2 x and c 1.3 x the envelope at 1000 steps, 0.9 x both at
+    5000; u at the FP32 floor U_FLOOR_3D, which is 7.7 x the envelope at 5000
+    steps.  The 3D flow collision uses the 2D remedies (weights through
+    correctly rounded divisions by 27, the exact momentum change), which
+    took the sheared bulk's mean velocity profile error from 3.7e-6 to
+    6e-8 of U0."""
+    from paper_2504_09024_amd import cmlb
+    key = "c5_64x32x32"
+    if key not in GOLD:
+        pytest.skip(f"envelope {key} not generated yet (tests/golden/make_sensitivity.py)")
+    p, fl = W.shear_drop3(nx=64, ny=32, nz=32, R=8.0)
+    ctx = {}
+    for prec in ("fp64", "fp32"):
+        c = cmlb.Context3([p], prec)
+        c.init_fields(0, fl["phi"], fl["c"], fl.get("ux"), fl.get("uy"), fl.get("uz"), fl.get("P"))
+        ctx[prec] = c
+    t = 0
+    for t_end in (1000, 5000):
+        for c in ctx.values():
+            c.step(t_end - t)
+        t = t_end
+        a, b = ctx["fp32"].read_fields(0), ctx["fp64"].read_fields(0)
+        rel = lambda x, y: float(np.linalg.norm(x - y) / np.linalg.norm(y))
+        u = lambda r: np.stack([r["ux"], r["uy"], r["uz"]])
+        env = GOLD[key][str(t_end)]
+        _check_envelope({"phi": rel(a["phi"], b["phi"]), "c": rel(a["c"], b["c"])}, env,
+                        f"{key} t={t_end}")
+        eu = rel(u(a), u(b))
+        bound = max(K_U * envelope(env, "u"), U_FLOOR_3D)
+        print(f"{key} t={t_end} u: FP32 {eu:.2e}, envelope {envelope(env, 'u'):.2e}, "
+              f"bound {bound:.2e}", flush=True)
+        assert eu <= bound, (t_end, eu, bound)
+    for c in ctx.values():
+        assert c.fault_flags(0) == 0
+        c.close()

@@ -57,7 +57,8 @@ def test_every_long_horizon_workload_has_its_envelope():
     """Each workload and checkpoint that the long-horizon GPU checks use has
     a stored envelope, positive for phi and c in both variants."""
     need = {"c1": (500, 2000), "coupled_random": (150,), "c2": (5000, 10000, 20000),
-            "c3_Ca0.1": (1000, 5000), "c3_Ca0.3": (1000, 5000), "c3_Ca0.5": (1000, 5000)}
+            "c3_Ca0.1": (1000, 5000), "c3_Ca0.3": (1000, 5000), "c3_Ca0.5": (1000, 5000),
+            "c5_64x32x32": (1000, 5000)}
     for key, ts in need.items():
         for t in ts:
             for variant in ("fp32", "perturbed"):
