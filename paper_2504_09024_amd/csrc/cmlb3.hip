@@ -386,8 +386,14 @@ int cmlb3_create(const cmlb3_sim_params* params, int32_t n_sims, int32_t precisi
             d.scale_f = 0.5 / pow2_floor3(std::fabs(phio) * 1.0000001);
             if (!(d.scale_f > 0.0) || !std::isfinite(d.scale_f)) d.scale_f = 1.0;
             d.scale_h = 16.0 / pow2_floor3(p.c_max > 0.0 ? p.c_max : 1.0);
+            // g holds 3 e_a.u P-sized velocity terms and the pressure
+            // deviation, which reaches cs^2 |rho_a - rho_b| across an
+            // interface when P starts at rho cs^2; values are kept near 32
+            // (binary16 overflows at 65504), speeds taken as O(u_wall),
+            // at least 1e-4 (as in 2D)
             const double uref = std::max(std::fabs(walls ? p.u_wall : 0.0), 1e-4);
-            d.scale_g = pow2_floor3(32.0 / (3.0 * uref));
+            const double dev = std::max(3.0 * uref, std::fabs(p.rho_a - p.rho_b) / 3.0);
+            d.scale_g = pow2_floor3(32.0 / dev);
         } else {
             d.qref_f = 0.0;
             d.scale_f = d.scale_h = d.scale_g = 1.0;
