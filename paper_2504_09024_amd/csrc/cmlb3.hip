@@ -53,6 +53,10 @@ void fill3(Consts3<T>& k, const cmlb3_sim_params& p, const Desc3& d, int walls) 
     k.scale_h = T(d.scale_h);
     k.inv_g = T(1.0 / d.scale_g);
     k.scale_g = T(d.scale_g);
+    // the weights rounded to T as on the device, then scaled by the power of
+    // two 1/scale_g (exact)
+    const T wn[4] = {T(8) / T(27), T(2) / T(27), T(1) / T(54), T(1) / T(216)};
+    for (int n = 0; n < 4; ++n) k.wdec3[n] = T(wn[n] * T(1.0 / d.scale_g));
     k.phi_a = T(p.phi_a);
     k.phi_b = T(p.phi_b);
     k.inv_dphi = T(1.0 / dphi);

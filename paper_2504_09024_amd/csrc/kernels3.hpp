@@ -86,6 +86,7 @@ __device__ __forceinline__ constexpr T wgt3(int a) {
 template <class T>
 struct Consts3 {
     T inv_f, qref_f, scale_f, inv_h, scale_h, inv_g, scale_g;
+    T wdec3[4];  // w_a / scale_g for n = 0..3 non-zero components (scaled g)
     T phi_a, phi_b, inv_dphi, phim, theta_k, thetac_k;
     T M_phi, D_s, omega_k, omega_c;
     T rho_b, drho, nu_b, dnu, inv_rho_b, omega_nu_b, omega_zeta;
@@ -302,8 +303,11 @@ __global__ __launch_bounds__(WG3) void k_moments3(const StepArgs3 a) {
 #pragma clang fp contract(off)
 #pragma unroll
         for (int q = 0; q < 27; ++q) {
+            // binary16: one product with w_a / scale_g (scale_g a power of
+            // two, so the same bits as w_a (v / scale_g))
             const T d = std::is_same_v<S, float> ? wgt3x27<T>(q) * v[q]
-                        : (Store<S>::scaled ? wgt3<T>(q) * (v[q] * k.inv_g) : wgt3<T>(q) * v[q]);
+                        : (Store<S>::scaled ? v[q] * k.wdec3[(q % 3 != 0) + ((q / 3) % 3 != 0) + (q / 9 != 0)]
+                                            : wgt3<T>(q) * v[q]);
             const int ex = EXd(q), ey = EYd(q), ez = EZd(q);
             r0 += d;
             if (ex) r1[0] += ex > 0 ? d : -d;
