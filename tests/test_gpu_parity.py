@@ -401,6 +401,19 @@ def test_device_copy_planes(gpu_lib, planes, nontemporal):
     assert bool((b[n:] == -1.0).all())
 
 
+def test_launch_costs(gpu_lib):
+    """cmlb_launch_costs (measurement aid): positive costs for a grid the
+    runtime can make resident, a graph kernel boundary cheaper than 1 ms,
+    and EINVAL for arguments outside its stated ranges."""
+    from paper_2504_09024_amd import cmlb
+    sync_us, node_us = cmlb.launch_costs(32, 64)
+    assert 0.0 < sync_us < 1000.0 and 0.0 < node_us < 1000.0, (sync_us, node_us)
+    for blocks, iters in ((0, 64), (2048, 64), (32, 10), (32, 17)):
+        with pytest.raises(cmlb.CmlbError) as e:
+            cmlb.launch_costs(blocks, iters)
+        assert e.value.code == cmlb.EINVAL
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
 def test_inventories_batched_match_single(oracle_mod, gpu_lib, prec):
     """cmlb_inventories over a ragged batch in one pair of launches: every
