@@ -575,12 +575,7 @@ __global__ __launch_bounds__(NW * 64, (Occupancy<T, NW>::waves_per_eu)) void k_s
                     // acts as a small steady force (FP32 against FP64, the
                     // velocity of the 1024 x 512 shear drop at Ca = 0.5 after
                     // 5000 steps: 6.0e-6 with this map in FP32, 7.9e-7 in FP64).
-                    double rd[9], qd[9];
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) rd[q] = r[q];
-                    pinv_dev<double>(rd, k.scale_g, qd);
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) qg[j][q] = T(qd[q]);
+                    pinv_dev_wide(r, k.scale_g, qg[j]);
                 } else {
                     pinv_dev(r, k.scale_g, qg[j]);
                 }

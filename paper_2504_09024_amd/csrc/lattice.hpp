@@ -192,6 +192,27 @@ __device__ __forceinline__ void pinv_dev(const T r[9], T scale, T s[9]) {
     s[7] = (p56 - r[6] - r[7]) * c5;
     s[8] = (m56 - r[6] + r[7]) * c5;
 }
+// The same map for FP32 values evaluated in FP64 (the same expressions, so
+// the same bits as pinv_dev<double> of the widened values), each result
+// rounded to FP32 once.
+__device__ __forceinline__ void pinv_dev_wide(const float r[9], float scale, float s[9]) {
+    const double c0 = double(scale) * 2.25;
+    const double c1 = double(scale) * 4.5;
+    const double c5 = double(scale) * 9.0;
+    const double r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5], r6 = r[6], r7 = r[7],
+                 r8 = r[8];
+    const double r37 = r3 - r8, r48 = r4 - r8;
+    s[0] = float((double(r[0]) - r3 - r4 + r8) * c0);
+    s[1] = float((r1 + r37 - r7) * c1);
+    s[2] = float((r2 + r48 - r6) * c1);
+    s[3] = float((-r1 + r37 + r7) * c1);
+    s[4] = float((-r2 + r48 + r6) * c1);
+    const double p56 = r5 + r8, m56 = r8 - r5;
+    s[5] = float((p56 + r6 + r7) * c5);
+    s[6] = float((m56 + r6 - r7) * c5);
+    s[7] = float((p56 - r6 - r7) * c5);
+    s[8] = float((m56 - r6 + r7) * c5);
+}
 // the same added to base (the node's zeroth moment in storage units), in
 // one expression per value so that each is a single multiply-add
 template <class T>
