@@ -50,7 +50,10 @@ typedef enum {
 } cmlb_status;
 
 /* Storage precision of the populations.  Arithmetic is FP64 for
- * CMLB_FP64 and FP32 otherwise; inventories are always FP64. */
+ * CMLB_FP64 and FP32 otherwise, except that CMLB_FP32 maps the flow
+ * lattice's post-collision moments back to populations in FP64 (its stored
+ * values then carry only the rounding of the store); inventories are
+ * always FP64. */
 typedef enum {
     CMLB_FP64 = 0,
     CMLB_FP32 = 1, /* FP32 deviations from the rest state, scaled by 1/w_a */
