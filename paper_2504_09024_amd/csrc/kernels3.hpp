@@ -425,7 +425,6 @@ __device__ __forceinline__ T mdep3(int a, int b, int c, T ux, T uy, T uz) {
             const T u2 = u[i] * u[i];
             const T cd = zero_c ? T(0) : C * u2;
             D = zero_d ? cd : (zero_c ? D * (C3<T>::cs2 + u2) : D * (C3<T>::cs2 + u2) + cd);
-            if (zero_c && zero_d) D = T(0);
             zero_d = zero_d && zero_c;
             if (!zero_c) C = C * C3<T>::cs2;
         }
